@@ -1,0 +1,196 @@
+/*
+ * Population-annealing CPU oracle: the integer core.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded C that shares no
+ * code with the HIP library.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it.
+ *
+ * What lives here (everything else of the oracle is in pa_oracle.py):
+ *   - Philox4x32-10, written from its published definition (Salmon, Moraes,
+ *     Dror & Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11):
+ *     ten rounds of two 32x32->64 multiplies with the round constants
+ *     0xD2511F53 / 0xCD9E8D57 and a Weyl key schedule 0x9E3779B9 / 0xBB67AE85.
+ *   - the random streams the method draws from (initial spins, Metropolis
+ *     uniforms, resampling uniforms), each a fixed map of (seed, indices)
+ *     to a Philox counter;
+ *   - simple-sampling initialisation at beta_0 = 0 (Sec. "Algorithm", step 1);
+ *   - checkerboard single-spin-flip Metropolis with acceptance
+ *     min[1, exp(-beta dE)] (Sec. "Spin updates");
+ *   - the energy and magnetisation of each replica (Sec. "Model and
+ *     observables", Eq. hamiltonian with J = 1, periodic L x L).
+ *
+ * Spin storage is replica-major and unpacked: spins[r * N + site], each +1 or
+ * -1, site = y * L + x.
+ */
+#include <stdint.h>
+#include <stddef.h>
+
+/* ---------------- Philox4x32-10 ---------------- */
+
+static void philox_round(uint32_t c[4], const uint32_t k[2]) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c[1] ^ k[0];
+    uint32_t n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+}
+
+void oracle_philox4x32_10(uint32_t key0, uint32_t key1, const uint32_t ctr[4], uint32_t out[4]) {
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key0, key1};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(c, k);
+    }
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = c[2];
+    out[3] = c[3];
+}
+
+/* ---------------- random streams ----------------
+ * key = (seed mod 2^32, seed div 2^32).  The fourth counter word carries a
+ * stream tag in its top nibble.  Replica slot r belongs to group g = r / 64
+ * and is lane r % 64 of that group.
+ *   INIT     (site, g, 0, 0x2000_0000): bits x0 | x1<<32, bit lane = 1 -> +1
+ *   SWEEP    (w, g, h, 0x1000_0000 | p), p = 0..15: planes 2p = x0 | x1<<32
+ *            and 2p+1 = x2 | x3<<32; the uniform of lane l is the 32-bit
+ *            integer whose bit (31 - b) is bit l of plane b.  w is the site's
+ *            index within its colour, h the global half-sweep index.
+ *   RESAMPLE (j >> 2, i, 0, 0x3000_0000): the uniform of parent j at step i
+ *            is output word j & 3.
+ *   MULTI    (d >> 1, i, 0, 0x4000_0000): the 64-bit uniform of draw d at
+ *            step i is x0 | x1<<32 (d even) or x2 | x3<<32 (d odd).
+ */
+#define TAG_SWEEP 0x10000000u
+#define TAG_INIT 0x20000000u
+#define TAG_RESAMPLE 0x30000000u
+#define TAG_MULTI 0x40000000u
+
+static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t out[4]) {
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    oracle_philox4x32_10((uint32_t)seed, (uint32_t)(seed >> 32), ctr, out);
+}
+
+uint32_t oracle_sweep_uniform(uint64_t seed, uint32_t w, uint32_t g, uint32_t h, uint32_t lane) {
+    uint32_t u = 0;
+    for (uint32_t p = 0; p < 16; ++p) {
+        uint32_t x[4];
+        draw(seed, w, g, h, TAG_SWEEP | p, x);
+        uint64_t plane_a = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+        uint64_t plane_b = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+        uint32_t bit_a = (uint32_t)((plane_a >> lane) & 1u);
+        uint32_t bit_b = (uint32_t)((plane_b >> lane) & 1u);
+        u |= bit_a << (31u - 2u * p);
+        u |= bit_b << (30u - 2u * p);
+    }
+    return u;
+}
+
+uint32_t oracle_resample_uniform(uint64_t seed, uint32_t step, uint32_t j) {
+    uint32_t x[4];
+    draw(seed, j >> 2, step, 0, TAG_RESAMPLE, x);
+    return x[j & 3u];
+}
+
+uint64_t oracle_multinomial_uniform(uint64_t seed, uint32_t step, uint32_t d) {
+    uint32_t x[4];
+    draw(seed, d >> 1, step, 0, TAG_MULTI, x);
+    if ((d & 1u) == 0)
+        return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    return (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+}
+
+/* ---------------- the model ---------------- */
+
+/* Simple sampling at beta_0 = 0: every spin of every replica is +1 or -1 with
+ * probability 1/2, independently. */
+void oracle_init_spins(uint64_t seed, int L, int R, int8_t *spins) {
+    int N = L * L;
+    for (int r = 0; r < R; ++r) {
+        for (int site = 0; site < N; ++site) {
+            uint32_t x[4];
+            draw(seed, (uint32_t)site, (uint32_t)(r / 64), 0, TAG_INIT, x);
+            uint64_t bits = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+            spins[(size_t)r * N + site] = ((bits >> (r % 64)) & 1u) ? (int8_t)1 : (int8_t)-1;
+        }
+    }
+}
+
+/* E = -sum over nearest-neighbour pairs of s_i s_j (each bond once, via the
+ * right and down neighbour of every site); M = sum of spins. */
+void oracle_energy_magnetisation(int L, int R, const int8_t *spins, int32_t *E, int32_t *M) {
+    int N = L * L;
+    for (int r = 0; r < R; ++r) {
+        const int8_t *s = spins + (size_t)r * N;
+        int32_t e = 0, m = 0;
+        for (int y = 0; y < L; ++y) {
+            for (int x = 0; x < L; ++x) {
+                int here = s[y * L + x];
+                int right = s[y * L + (x + 1) % L];
+                int down = s[((y + 1) % L) * L + x];
+                e -= here * (right + down);
+                m += here;
+            }
+        }
+        E[r] = e;
+        M[r] = m;
+    }
+}
+
+/* One Metropolis attempt's energy change for flipping spin s with neighbour
+ * field h: dE = 2 s h. */
+int oracle_delta_energy(int s, int h) { return 2 * s * h; }
+
+/*
+ * theta checkerboard sweeps at inverse temperature beta_i of step i >= 1.
+ * One sweep attempts every site of colour 0 = (x + y) even, then every site of
+ * colour 1.  A flip with dE <= 0 is always accepted; otherwise it is accepted
+ * iff u < exp(-beta dE) with u = u32 / 2^32.  The caller passes the exact
+ * integer thresholds t4 = ceil(2^32 exp(-4 beta)) and t8 = ceil(2^32
+ * exp(-8 beta)) (both in [1, 2^32]); for an integer u32, u32 / 2^32 < p holds
+ * exactly when u32 < ceil(2^32 p).
+ */
+void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int theta,
+                   uint64_t t4, uint64_t t8) {
+    int N = L * L;
+    int half = L / 2;
+    for (int sweep = 0; sweep < theta; ++sweep) {
+        for (int colour = 0; colour < 2; ++colour) {
+            uint32_t h = (uint32_t)(2 * (theta * (step - 1) + sweep) + colour);
+            for (int r = 0; r < R; ++r) {
+                int8_t *s = spins + (size_t)r * N;
+                for (int y = 0; y < L; ++y) {
+                    for (int x = 0; x < L; ++x) {
+                        if (((x + y) & 1) != colour)
+                            continue;
+                        int here = s[y * L + x];
+                        int field = s[y * L + (x + 1) % L] + s[y * L + (x + L - 1) % L] +
+                                    s[((y + 1) % L) * L + x] + s[((y + L - 1) % L) * L + x];
+                        int dE = oracle_delta_energy(here, field);
+                        int flip;
+                        if (dE <= 0) {
+                            flip = 1;
+                        } else {
+                            uint32_t w = (uint32_t)(y * half + x / 2);
+                            uint64_t u = oracle_sweep_uniform(seed, w, (uint32_t)(r / 64), h,
+                                                              (uint32_t)(r % 64));
+                            uint64_t t = (dE == 4) ? t4 : t8;
+                            flip = u < t;
+                        }
+                        if (flip)
+                            s[y * L + x] = (int8_t)(-here);
+                    }
+                }
+            }
+        }
+    }
+}

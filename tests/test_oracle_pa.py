@@ -1,0 +1,130 @@
+"""Pins for whole oracle runs (no GPU): free energy, energy and specific heat
+against the exact L = 4 results, family statistics on hand-built populations,
+and the invariants the method guarantees."""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import pa_oracle as po
+from workloads import linear_schedule
+
+
+def test_family_stats_special_cases():
+    # all distinct: rho_t = rho_s = 1; one family: rho_t = rho_s = R_i;
+    # k equal families of size c: rho_t = rho_s = c
+    assert po.family_stats(np.arange(10)) == (10, 10, 1.0, pytest.approx(1.0))
+    f, s2, rt, rs = po.family_stats(np.zeros(12, dtype=np.int32))
+    assert (f, s2, rt) == (1, 144, 12.0) and abs(rs - 12) < 1e-12
+    f, s2, rt, rs = po.family_stats(np.repeat(np.arange(4), 5))
+    assert (f, s2, rt) == (4, 100, 5.0) and abs(rs - 5) < 1e-12
+    # a hand-computed mixed case: sizes 3, 2, 1 out of 6
+    f, s2, rt, rs = po.family_stats(np.array([0, 0, 0, 2, 2, 5]))
+    S = -(0.5 * math.log(0.5) + (1 / 3) * math.log(1 / 3) + (1 / 6) * math.log(1 / 6))
+    assert (f, s2) == (3, 14) and abs(rt - 14 / 6) < 1e-15 and abs(rs - 6 / math.exp(S)) < 1e-12
+    # Renyi ordering 1 <= rho_s <= rho_t <= R_i on random partitions
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        fam = np.sort(rng.integers(0, 30, size=50))
+        _, _, rt, rs = po.family_stats(fam)
+        assert 1 - 1e-12 <= rs <= rt + 1e-12 <= 50 + 1e-12
+
+
+def test_observable_formulas_match_population_moments():
+    L, R = 6, 200
+    o = po.OracleRun(L, R, 0, 3, "nearest")
+    beta = 0.37
+    (sE, sE2, sM, sM2), (e, cv, m, chi) = po.observables(L, beta, o.E, o.M)
+    E, M = o.E.astype(np.float64), o.M.astype(np.float64)
+    N = L * L
+    assert abs(e - E.mean() / N) < 1e-14
+    assert abs(cv - beta ** 2 * E.var() / N) < 1e-12
+    assert abs(m - np.abs(M).mean() / N) < 1e-14
+    assert abs(chi - beta * (np.mean(M * M) - np.abs(M).mean() ** 2) / N) < 1e-12
+
+
+def test_run_invariants_nearest():
+    L, R = 6, 300
+    betas = linear_schedule(0.6, 12)
+    o = po.run(L, R, betas, 2, 21, "nearest")
+    recs = o.records
+    assert abs(recs[0].minus_beta_F - L * L * math.log(2)) < 1e-12
+    f_prev = R
+    acc = recs[0].minus_beta_F
+    for r in recs[1:]:
+        assert r.n_families <= f_prev
+        f_prev = r.n_families
+        assert 1 - 1e-12 <= r.rho_s <= r.rho_t + 1e-12 <= r.R_i + 1e-12
+        acc += r.ln_Q
+        assert abs(acc - r.minus_beta_F) < 1e-9
+    assert np.all(np.diff(o.fam) >= 0)
+    assert np.all(o.E % 4 == 0)
+    assert o.last_counts.sum() == len(o.E)
+
+
+def test_theta_zero_keeps_copies_of_initial_replicas():
+    L, R, seed = 6, 200, 4
+    init = po.init_spins(seed, L, R)
+    o = po.run(L, R, linear_schedule(0.5, 6), 0, seed, "multinomial")
+    assert len(o.E) == R
+    for j in range(len(o.E)):
+        assert np.array_equal(o.spins[j], init[o.fam[j]])
+
+
+def test_runs_are_deterministic():
+    a = po.run(4, 128, linear_schedule(0.4, 5), 2, 9, "nearest").records
+    b = po.run(4, 128, linear_schedule(0.4, 5), 2, 9, "nearest").records
+    assert a == b
+
+
+@pytest.mark.slow
+def test_free_energy_energy_and_specific_heat_match_exact_L4():
+    """PA at L = 4 reproduces ln Z(beta), e and C_V within statistical error.
+
+    -beta F is Eq. (free-emergy-estimator); its spread over seeds gives the error
+    bar.  A finite population biases ln Z by O(1/R); with R = 3000 that bias is
+    far below the tolerance used here.
+    """
+    L, R = 4, 3000
+    betas = linear_schedule(0.7, 35)
+    seeds = [101, 102, 103, 104]
+    F = {i: [] for i in (10, 20, 35)}
+    e_end, cv_end = [], []
+    for s in seeds:
+        o = po.run(L, R, betas, 4, s, "nearest")
+        for i in F:
+            F[i].append(o.records[i].minus_beta_F)
+        e_end.append(o.records[-1].e)
+        cv_end.append(o.records[-1].c_v)
+    for i, vals in F.items():
+        exact_lnz = float(exact.ln_z_kaufman(L, betas[i]))
+        mean = np.mean(vals)
+        sd = max(np.std(vals, ddof=1), 1e-3)
+        assert abs(mean - exact_lnz) < 5 * sd / math.sqrt(len(vals)) + 0.01, (i, mean, exact_lnz)
+    e_ex = float(exact.energy_per_spin(L, betas[-1]))
+    cv_ex = float(exact.specific_heat(L, betas[-1]))
+    assert abs(np.mean(e_end) - e_ex) < 0.02
+    assert abs(np.mean(cv_end) - cv_ex) < 0.1 * cv_ex
+
+
+def test_overlap_matches_gaussian_closed_form_and_paper_values(golden_dir):
+    """alpha for equal-width Gaussians is 2 Phi(-dbeta sigma / 2).
+
+    With sigma_E of the L = 32 lattice at beta_c (from the exact C_V) this
+    gives ~0.32 at dbeta = 0.02 and ~0.014 at 0.05; the paper quotes "about
+    0.3" and "less than 10 %" (Sec. "Bias with resampling").
+    """
+    import json, os
+    pv = json.load(open(os.path.join(golden_dir, "paper_values.json")))["overlap_L32_beta_c"]
+    bc = 0.5 * math.log(1 + math.sqrt(2))
+    sigma = math.sqrt(float(exact.specific_heat(32, bc)) * 1024) / bc
+    rng = np.random.default_rng(1)
+    E = np.round(rng.normal(-1450, sigma, size=40000) / 4) * 4
+    for db, key in ((0.02, "dbeta_0.02"), (0.05, "dbeta_0.05")):
+        a = po.overlap(E.astype(np.int64), db)
+        closed = math.erfc(db * sigma / 2 / math.sqrt(2))
+        assert abs(a - closed) < 0.02
+    assert abs(po.overlap(E.astype(np.int64), 0.02) - pv["dbeta_0.02"]["value"]) < 0.05
+    assert po.overlap(E.astype(np.int64), 0.05) < pv["dbeta_0.05"]["value"]
