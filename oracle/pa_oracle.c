@@ -157,10 +157,11 @@ int oracle_delta_energy(int s, int h) { return 2 * s * h; }
  * iff u < exp(-beta dE) with u = u32 / 2^32.  The caller passes the exact
  * integer thresholds t4 = ceil(2^32 exp(-4 beta)) and t8 = ceil(2^32
  * exp(-8 beta)) (both in [1, 2^32]); for an integer u32, u32 / 2^32 < p holds
- * exactly when u32 < ceil(2^32 p).
+ * exactly when u32 < ceil(2^32 p).  spins holds R replicas occupying slots
+ * slot0 .. slot0 + R - 1 of the population (their slots select their uniforms).
  */
 void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int theta,
-                   uint64_t t4, uint64_t t8) {
+                   uint64_t t4, uint64_t t8, int slot0) {
     int N = L * L;
     int half = L / 2;
     for (int sweep = 0; sweep < theta; ++sweep) {
@@ -168,6 +169,7 @@ void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int the
             uint32_t h = (uint32_t)(2 * (theta * (step - 1) + sweep) + colour);
             for (int r = 0; r < R; ++r) {
                 int8_t *s = spins + (size_t)r * N;
+                int slot = slot0 + r; /* the replica's position in the population */
                 for (int y = 0; y < L; ++y) {
                     for (int x = 0; x < L; ++x) {
                         if (((x + y) & 1) != colour)
@@ -181,8 +183,8 @@ void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int the
                             flip = 1;
                         } else {
                             uint32_t w = (uint32_t)(y * half + x / 2);
-                            uint64_t u = oracle_sweep_uniform(seed, w, (uint32_t)(r / 64), h,
-                                                              (uint32_t)(r % 64));
+                            uint64_t u = oracle_sweep_uniform(seed, w, (uint32_t)(slot / 64), h,
+                                                              (uint32_t)(slot % 64));
                             uint64_t t = (dE == 4) ? t4 : t8;
                             flip = u < t;
                         }

@@ -92,7 +92,7 @@ def lib():
         L.oracle_energy_magnetisation.restype = None
         L.oracle_delta_energy.argtypes = [i32, i32]
         L.oracle_delta_energy.restype = i32
-        L.oracle_sweeps.argtypes = [u64, i32, i32, p_i8, i32, i32, u64, u64]
+        L.oracle_sweeps.argtypes = [u64, i32, i32, p_i8, i32, i32, u64, u64, i32]
         L.oracle_sweeps.restype = None
         _lib = L
     return _lib
@@ -145,12 +145,16 @@ def energy_magnetisation(L: int, spins: np.ndarray):
     return E, M
 
 
-def sweeps(seed: int, L: int, spins: np.ndarray, step: int, theta: int, t4: int, t8: int) -> None:
-    """theta checkerboard Metropolis sweeps, in place, for step >= 1."""
+def sweeps(seed: int, L: int, spins: np.ndarray, step: int, theta: int, t4: int, t8: int,
+           slot0: int = 0) -> None:
+    """theta checkerboard Metropolis sweeps, in place, for step >= 1.
+
+    spins[k] is the replica in population slot slot0 + k.
+    """
     assert spins.dtype == np.int8 and spins.flags.c_contiguous
     R = spins.shape[0]
     if R and theta:
-        lib().oracle_sweeps(seed, L, R, _ptr(spins, ctypes.c_int8), step, theta, t4, t8)
+        lib().oracle_sweeps(seed, L, R, _ptr(spins, ctypes.c_int8), step, theta, t4, t8, slot0)
 
 
 # ---------------------------------------------------------------- decisions

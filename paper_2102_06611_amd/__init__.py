@@ -1,0 +1,369 @@
+"""Population annealing for the 2D Ising model on AMD Instinct MI355X.
+
+A thin ctypes binding of libpa (include/pa.h).  Every step of the method runs
+in the library's HIP kernels; this module only marshals arguments.  PyTorch
+supplies device memory (the workspace) and the HIP stream.
+
+The functions keep the C names (pa_create, pa_anneal_step, ...); ``Run`` and
+``Batch`` bundle a handle with its torch-allocated workspace.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpa.so")
+
+PA_OK = 0
+PA_ERR_ARG, PA_ERR_NOMEM, PA_ERR_DEVICE, PA_ERR_CAPACITY = -1, -2, -3, -4
+PA_ERR_DONE, PA_ERR_STATE, PA_ERR_NUMERIC = -5, -6, -7
+PA_RESAMPLE_NEAREST, PA_RESAMPLE_MULTINOMIAL, PA_RESAMPLE_NONE = 0, 1, 2
+PA_LAYOUT_INT8, PA_LAYOUT_MSC64 = 0, 1
+PA_MLP_IN, PA_MLP_HIDDEN = 35, 64
+PA_MLP_PARAMS = 64 * 35 + 64 + 64 * 64 + 64 + 64 + 1
+
+RESAMPLE = {"nearest": PA_RESAMPLE_NEAREST, "multinomial": PA_RESAMPLE_MULTINOMIAL,
+            "none": PA_RESAMPLE_NONE}
+LAYOUT = {"int8": PA_LAYOUT_INT8, "msc64": PA_LAYOUT_MSC64}
+_STATUS = {0: "PA_OK", -1: "PA_ERR_ARG", -2: "PA_ERR_NOMEM", -3: "PA_ERR_DEVICE",
+           -4: "PA_ERR_CAPACITY", -5: "PA_ERR_DONE", -6: "PA_ERR_STATE", -7: "PA_ERR_NUMERIC"}
+
+
+class pa_config(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("betas", ctypes.POINTER(ctypes.c_double)), ("n_steps", ctypes.c_int32),
+                ("theta", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("resample", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("capacity", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pa_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int32), ("R_i", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("sum_E", ctypes.c_int64), ("sum_E2", ctypes.c_int64),
+                ("sum_absM", ctypes.c_int64), ("sum_M2", ctypes.c_int64),
+                ("e", ctypes.c_double), ("c_v", ctypes.c_double), ("m", ctypes.c_double),
+                ("chi", ctypes.c_double), ("ln_Q", ctypes.c_double),
+                ("minus_beta_F", ctypes.c_double), ("n_families", ctypes.c_int64),
+                ("sum_fam2", ctypes.c_int64), ("sum_cnt2", ctypes.c_int64),
+                ("rho_t", ctypes.c_double), ("rho_s", ctypes.c_double),
+                ("rho_t_step", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+# (name, restype, argtypes); every entry point of include/pa.h
+_vp, _i32, _i64, _u32, _u64, _dbl, _flt = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                            ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                                            ctypes.c_float)
+_P = ctypes.POINTER
+SIGNATURES = {
+    "pa_workspace_size": (_i32, [_P(pa_config), _P(ctypes.c_size_t)]),
+    "pa_create": (_i32, [_P(pa_config), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "pa_anneal_step": (_i32, [_vp]),
+    "pa_anneal_step_to": (_i32, [_vp, _dbl]),
+    "pa_run": (_i32, [_vp, _i32]),
+    "pa_sync": (_i32, [_vp]),
+    "pa_observables": (_i32, [_vp, _i32, _P(pa_obs)]),
+    "pa_current": (_i32, [_vp, _P(_i32), _P(_i32)]),
+    "pa_energy_histogram": (_i32, [_vp, _P(_i32), _i32, _P(_i32), _P(_i32)]),
+    "pa_copy_counts": (_i32, [_vp, _P(_i32), _i64, _P(_i64)]),
+    "pa_get_population": (_i32, [_vp, _i32, _i32, _P(ctypes.c_int8), _P(_i32), _P(_i32), _P(_i32)]),
+    "pa_get_state": (_i32, [_vp, _vp, ctypes.c_size_t, _P(ctypes.c_size_t)]),
+    "pa_set_state": (_i32, [_vp, _vp, ctypes.c_size_t]),
+    "pa_set_population": (_i32, [_vp, _i32, _i32, _P(ctypes.c_int8), _P(_i32), _dbl]),
+    "pa_overlap": (_i32, [_vp, _dbl, _P(_dbl)]),
+    "pa_adaptive_dbeta": (_i32, [_vp, _dbl, _dbl, _P(_dbl)]),
+    "pa_destroy": (None, [_vp]),
+    "pa_last_error": (ctypes.c_char_p, [_vp]),
+    "pa_batch_workspace_size": (_i32, [_P(pa_config), _i32, _P(ctypes.c_size_t)]),
+    "pa_batch_create": (_i32, [_P(pa_config), _i32, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "pa_batch_run": (_i32, [_vp, _i32]),
+    "pa_batch_observables": (_i32, [_vp, _i32, _i32, _P(pa_obs)]),
+    "pa_batch_sync": (_i32, [_vp]),
+    "pa_batch_destroy": (None, [_vp]),
+    "pa_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "pa_philox4x32_10": (_i32, [_u32, _u32, _vp, _i64, _vp, _vp]),
+    "pa_features": (_i32, [_vp, _vp]),
+    "pa_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp]),
+    "pa_mlp_backward": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "pa_mlp_train_step": (_i32, [_vp, _vp, _vp, _vp, _i32, _flt, _i32, _vp, _vp]),
+    "pa_learned_dbeta": (_i32, [_vp, _vp, _dbl, _dbl, _dbl, _vp, _P(_dbl), _P(_i32)]),
+    "pa_anneal_step_adaptive": (_i32, [_vp, _dbl, _dbl]),
+    "pa_anneal_step_learned": (_i32, [_vp, _vp, _dbl, _dbl, _dbl]),
+    "pa_schedule_log": (_i32, [_vp, _vp, _vp, _P(_i32), _P(_dbl), _i32, _P(_i32)]),
+}
+
+
+def lib():
+    """The loaded libpa; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpa.so is missing at %s: run __graft_entry__.build() or "
+                               "python paper_2102_06611_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, handle=None, batch: bool = False):
+    if status != PA_OK:
+        L = lib()
+        msg = (L.pa_batch_last_error(handle) if batch else L.pa_last_error(handle)) or b""
+        raise PAError(status, msg.decode(errors="replace"))
+
+
+def make_config(L: int, R: int, betas: Optional[Sequence[float]], theta: int, seed: int,
+                resample: str = "nearest", layout: str = "msc64", capacity: int = 0,
+                n_steps: Optional[int] = None):
+    """A pa_config plus the double array it points to (keep both alive)."""
+    arr = None
+    if betas is not None:
+        arr = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+        n = len(arr) - 1
+    else:
+        n = int(n_steps)
+    cfg = pa_config(L, R, arr.ctypes.data_as(_P(ctypes.c_double)) if arr is not None else None,
+                    n, theta, seed, RESAMPLE[resample], LAYOUT[layout], capacity, 0)
+    return cfg, arr
+
+
+def _stream_handle(stream):
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+
+
+class Run:
+    """One population-annealing run: a pa_ctx with its torch workspace."""
+
+    def __init__(self, L: int, R: int, betas: Optional[Sequence[float]], theta: int, seed: int,
+                 resample: str = "nearest", layout: str = "msc64", capacity: int = 0,
+                 n_steps: Optional[int] = None, device: str = "cuda:0", stream=None):
+        import torch
+        self.L, self.N, self.R = L, L * L, R
+        self.cfg, self._betas = make_config(L, R, betas, theta, seed, resample, layout,
+                                            capacity, n_steps)
+        nbytes = ctypes.c_size_t()
+        _check(lib().pa_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().pa_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
+                               nbytes.value, _stream_handle(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping
+    def anneal_step(self):
+        _check(lib().pa_anneal_step(self.h), self.h)
+
+    def anneal_step_to(self, beta_next: float):
+        _check(lib().pa_anneal_step_to(self.h, float(beta_next)), self.h)
+
+    def run(self, n_steps: int):
+        _check(lib().pa_run(self.h, int(n_steps)), self.h)
+
+    def sync(self):
+        _check(lib().pa_sync(self.h), self.h)
+
+    # -- results
+    def observables(self, step: int) -> dict:
+        o = pa_obs()
+        _check(lib().pa_observables(self.h, int(step), ctypes.byref(o)), self.h)
+        return o.as_dict()
+
+    def current(self):
+        s, r = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pa_current(self.h, ctypes.byref(s), ctypes.byref(r)), self.h)
+        return s.value, r.value
+
+    def energy_histogram(self):
+        kmin, nb = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pa_energy_histogram(self.h, None, 0, ctypes.byref(kmin), ctypes.byref(nb)), self.h)
+        out = np.zeros(nb.value, dtype=np.int32)
+        _check(lib().pa_energy_histogram(self.h, out.ctypes.data_as(_P(_i32)), nb.value,
+                                         ctypes.byref(kmin), ctypes.byref(nb)), self.h)
+        return kmin.value, out
+
+    def copy_counts(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        _check(lib().pa_copy_counts(self.h, None, 0, ctypes.byref(n)), self.h)
+        out = np.zeros(n.value, dtype=np.int32)
+        _check(lib().pa_copy_counts(self.h, out.ctypes.data_as(_P(_i32)), n.value,
+                                    ctypes.byref(n)), self.h)
+        return out
+
+    def population(self, first: int = 0, count: Optional[int] = None, spins: bool = True):
+        """(spins [count, N] int8, fam, E, M) of the current population."""
+        _, R_i = self.current()
+        if count is None:
+            count = R_i - first
+        s = np.zeros((count, self.N), dtype=np.int8) if spins else None
+        fam = np.zeros(count, dtype=np.int32)
+        E = np.zeros(count, dtype=np.int32)
+        M = np.zeros(count, dtype=np.int32)
+        _check(lib().pa_get_population(
+            self.h, first, count, s.ctypes.data_as(_P(ctypes.c_int8)) if spins else None,
+            fam.ctypes.data_as(_P(_i32)), E.ctypes.data_as(_P(_i32)),
+            M.ctypes.data_as(_P(_i32))), self.h)
+        return s, fam, E, M
+
+    def set_population(self, step: int, spins: np.ndarray, fam: np.ndarray, minus_beta_F: float):
+        spins = np.ascontiguousarray(spins, dtype=np.int8)
+        fam = np.ascontiguousarray(fam, dtype=np.int32)
+        _check(lib().pa_set_population(self.h, int(step), spins.shape[0],
+                                       spins.ctypes.data_as(_P(ctypes.c_int8)),
+                                       fam.ctypes.data_as(_P(_i32)), float(minus_beta_F)), self.h)
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(lib().pa_get_state(self.h, None, 0, ctypes.byref(n)), self.h)
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().pa_get_state(self.h, buf, n.value, ctypes.byref(n)), self.h)
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        _check(lib().pa_set_state(self.h, blob, len(blob)), self.h)
+
+    def overlap(self, dbeta: float) -> float:
+        a = ctypes.c_double()
+        _check(lib().pa_overlap(self.h, float(dbeta), ctypes.byref(a)), self.h)
+        return a.value
+
+    def adaptive_dbeta(self, alpha_target: float, dbeta_max: float) -> float:
+        d = ctypes.c_double()
+        _check(lib().pa_adaptive_dbeta(self.h, float(alpha_target), float(dbeta_max),
+                                       ctypes.byref(d)), self.h)
+        return d.value
+
+    def features(self, dev_feat) -> None:
+        _check(lib().pa_features(self.h, ctypes.c_void_p(dev_feat.data_ptr())), self.h)
+
+    def anneal_step_adaptive(self, alpha_target: float, beta_final: float):
+        _check(lib().pa_anneal_step_adaptive(self.h, float(alpha_target), float(beta_final)), self.h)
+
+    def anneal_step_learned(self, params, alpha_min: float, alpha_target: float,
+                            beta_final: float):
+        _check(lib().pa_anneal_step_learned(self.h, ctypes.c_void_p(params.data_ptr()),
+                                            float(alpha_min), float(alpha_target),
+                                            float(beta_final)), self.h)
+
+    def schedule_log(self, dev_feat=None, dev_target=None):
+        """(n, accepted[n], alpha[n]); features/targets go to the given device tensors."""
+        n = ctypes.c_int32()
+        _check(lib().pa_schedule_log(self.h, None, None, None, None, 0, ctypes.byref(n)), self.h)
+        acc = np.zeros(n.value, dtype=np.int32)
+        alpha = np.zeros(n.value, dtype=np.float64)
+        _check(lib().pa_schedule_log(
+            self.h, ctypes.c_void_p(dev_feat.data_ptr()) if dev_feat is not None else None,
+            ctypes.c_void_p(dev_target.data_ptr()) if dev_target is not None else None,
+            acc.ctypes.data_as(_P(_i32)), alpha.ctypes.data_as(_P(_dbl)), n.value,
+            ctypes.byref(n)), self.h)
+        return n.value, acc, alpha
+
+    def learned_dbeta(self, params, alpha_min: float, alpha_target: float, dbeta_max: float,
+                      dev_feat=None):
+        d, acc = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().pa_learned_dbeta(
+            self.h, ctypes.c_void_p(params.data_ptr()), float(alpha_min), float(alpha_target),
+            float(dbeta_max), ctypes.c_void_p(dev_feat.data_ptr()) if dev_feat is not None else None,
+            ctypes.byref(d), ctypes.byref(acc)), self.h)
+        return d.value, bool(acc.value)
+
+
+class Batch:
+    """Independent runs of uneven (L, R) in one engine (pa_batch)."""
+
+    def __init__(self, specs: List[dict], device: str = "cuda:0", stream=None):
+        import torch
+        self._keep = []
+        cfgs = (pa_config * len(specs))()
+        for k, s in enumerate(specs):
+            cfg, arr = make_config(s["L"], s["R"], s["betas"], s["theta"], s["seed"],
+                                   s.get("resample", "nearest"), s.get("layout", "msc64"),
+                                   s.get("capacity", 0))
+            cfgs[k] = cfg
+            self._keep.append(arr)
+        self.n = len(specs)
+        nbytes = ctypes.c_size_t()
+        _check(lib().pa_batch_workspace_size(cfgs, self.n, ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().pa_batch_create(cfgs, self.n, ctypes.c_void_p(self.workspace.data_ptr()),
+                                     nbytes.value, _stream_handle(stream), ctypes.byref(h)))
+        self.h = h
+        self.stream = stream
+
+    def run(self, n_steps: int):
+        _check(lib().pa_batch_run(self.h, int(n_steps)), self.h, batch=True)
+
+    def sync(self):
+        _check(lib().pa_batch_sync(self.h), self.h, batch=True)
+
+    def observables(self, run: int, step: int) -> dict:
+        o = pa_obs()
+        _check(lib().pa_batch_observables(self.h, int(run), int(step), ctypes.byref(o)), self.h,
+               batch=True)
+        return o.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pa_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def philox4x32_10(key: int, ctr_dev, out_dev, stream=None):
+    """Device Philox4x32-10 over an [n, 4] uint32 (int32-typed) counter tensor."""
+    n = ctr_dev.shape[0]
+    _check(lib().pa_philox4x32_10(key & 0xFFFFFFFF, key >> 32, ctypes.c_void_p(ctr_dev.data_ptr()),
+                                  n, ctypes.c_void_p(out_dev.data_ptr()), _stream_handle(stream)))
+
+
+def mlp_forward(params, x, y, stream=None):
+    _check(lib().pa_mlp_forward(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                x.shape[0], ctypes.c_void_p(y.data_ptr()), _stream_handle(stream)))
+
+
+def mlp_backward(params, x, t, grad, loss, stream=None):
+    _check(lib().pa_mlp_backward(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(t.data_ptr()), x.shape[0],
+                                 ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
+                                 _stream_handle(stream)))
+
+
+def mlp_train_step(params, adam, x, t, lr: float, step: int, loss, stream=None):
+    _check(lib().pa_mlp_train_step(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(adam.data_ptr()),
+                                   ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                   x.shape[0], float(lr), int(step), ctypes.c_void_p(loss.data_ptr()),
+                                   _stream_handle(stream)))

@@ -1,0 +1,60 @@
+// Host-side launch descriptions shared by the engine and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "pa_device.hpp"
+
+namespace pa {
+
+struct MapInfo {
+    WorkMap map;  // device arrays
+    int total;    // blocks in the launch
+};
+
+struct SweepClass {
+    int L, N;
+    WorkMap map;
+    int total;
+    bool has_msc, has_int8;
+};
+
+struct LaunchCtx {
+    const RunDesc *runs;  // device array [n_runs]
+    int n_runs;
+    hipStream_t stream;
+    MapInfo slots;   // per run: nblk blocks of kSlotBlock slots
+    MapInfo groups;  // per run: G blocks, one per 64-replica group
+    std::vector<SweepClass> sweep_classes;  // one launch per distinct L
+    int sweep_threads;
+    bool any_nearest, any_multi;
+};
+
+hipError_t configure_kernels();
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
+hipError_t launch_init(const LaunchCtx &c);
+hipError_t launch_sweeps(const LaunchCtx &c, int init);
+hipError_t launch_reduce(const LaunchCtx &c);
+hipError_t launch_step(const LaunchCtx &c);
+hipError_t launch_hist_current(const LaunchCtx &c);
+hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta, double target, int mode);
+hipError_t launch_set_beta(const LaunchCtx &c, int r, int idx, double beta);
+hipError_t launch_unpack_group(const LaunchCtx &c, int r, int g, int N);
+hipError_t launch_pack_group(const LaunchCtx &c, int r, int g, int buf, int n_valid, int N);
+hipError_t launch_adopt_begin(const LaunchCtx &c, int r, int R_i);
+hipError_t launch_adopt_end(const LaunchCtx &c, int r, int step, double acc);
+hipError_t launch_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, int64_t n, uint32_t *out,
+                         hipStream_t stream);
+hipError_t launch_features(const LaunchCtx &c, int r, float *feat);
+hipError_t launch_schedule(const LaunchCtx &c, int r, const float *params, double alpha_min,
+                           double alpha_target, double dmax_or_final, int mode, float *feat_out);
+hipError_t launch_mlp_forward(const float *params, const float *x, int n, float *y,
+                              hipStream_t stream);
+hipError_t launch_mlp_backward(const float *params, const float *x, const float *t, int n,
+                               float *grad, float *loss, hipStream_t stream);
+hipError_t launch_adam_step(float *params, float *adam, const float *x, const float *t, int n,
+                            float lr, int step, float *loss, hipStream_t stream);
+
+}  // namespace pa

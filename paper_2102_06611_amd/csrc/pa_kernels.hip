@@ -1,0 +1,960 @@
+// HIP kernels of one population-annealing temperature step, batched over
+// independent runs (a single run is a batch of one).
+//
+// Step i (Sec. "Algorithm", steps 2-4), with the population entering the step
+// in buffer `cur` and the new one built in buffer `cur ^ 1`:
+//   k_begin        thresholds for beta_i, clear the energy histogram
+//   k_hist         histogram of E over the R_{i-1} parents
+//   k_norm         Q_i of Eq. (Q) over the histogram levels; per-level decision
+//                  integers for the copy counts (Eq. taus / resampling-factors)
+//   k_counts_*     copy counts r_j, block partial sums, R_i (last block)
+//   k_offsets      exclusive prefix sum of r_j (tree order of the children)
+//   k_gather       children <- parents: spins and family labels
+//   k_sweep        theta checkerboard Metropolis sweeps in LDS + E, M
+//   k_reduce       population sums, family statistics, record i (last block)
+#include <climits>
+
+#include "pa_block.hpp"
+#include "pa_device.hpp"
+#include "pa_internal.hpp"
+
+namespace pa {
+
+// ------------------------------------------------------------------ helpers
+
+// 4 int8 spins (+1 = 0x01, -1 = 0xFF) -> 4 bits, bit = 1 for +1.  Bit 7 of each
+// byte is moved to the top nibble by one multiply (no carries cross into it).
+__device__ __forceinline__ uint32_t spins_to_nibble(uint32_t d) {
+    uint32_t neg = (d >> 7) & 0x01010101u;
+    uint32_t dn = (neg * 0x10204080u) >> 28;
+    return ~dn & 0xFu;
+}
+// Inverse of spins_to_nibble.
+__device__ __forceinline__ uint32_t nibble_to_spins(uint32_t up4) {
+    uint32_t dn = ~up4 & 0xFu;
+    uint32_t spread = (dn & 1u) | ((dn & 2u) << 7) | ((dn & 4u) << 14) | ((dn & 8u) << 21);
+    return 0x01010101u | (spread * 0xFEu);
+}
+__device__ __forceinline__ uint32_t pack16(uint4 v) {
+    return spins_to_nibble(v.x) | (spins_to_nibble(v.y) << 4) | (spins_to_nibble(v.z) << 8) |
+           (spins_to_nibble(v.w) << 12);
+}
+__device__ __forceinline__ uint4 unpack16(uint32_t b) {
+    return uint4{nibble_to_spins(b & 0xF), nibble_to_spins((b >> 4) & 0xF),
+                 nibble_to_spins((b >> 8) & 0xF), nibble_to_spins((b >> 12) & 0xF)};
+}
+
+__device__ __forceinline__ uint64_t lane_mask(int n_valid) {
+    if (n_valid >= 64) return ~0ull;
+    if (n_valid <= 0) return 0ull;
+    return (1ull << n_valid) - 1ull;
+}
+
+// ------------------------------------------------------------------ init
+
+// Simple sampling at beta_0 = 0 (Sec. "Algorithm", step 1): spin lane of group
+// g at `site` is bit lane of x0 | x1 << 32 of Philox(site, g, 0, INIT).
+__global__ void k_init_population(const RunDesc *runs, WorkMap map) {
+    int g;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &g)];
+    if (g >= rd.G) return;
+    const uint64_t valid = lane_mask(rd.R - g * kLanes);
+    for (int site = threadIdx.x; site < rd.N; site += blockDim.x) {
+        U4 x = philox(rd.key0, rd.key1, (uint32_t)site, (uint32_t)g, 0u, kTagInit);
+        uint64_t bits = (((uint64_t)x.y << 32) | x.x) & valid;
+        size_t w = (size_t)g * rd.N + site;
+        if (rd.layout == PA_LAYOUT_MSC64) {
+            rd.ms[0][w] = bits;
+        } else {
+            uint4 *dst = reinterpret_cast<uint4 *>(rd.s8[0] + w * kLanes);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = unpack16((uint32_t)(bits >> (16 * q)) & 0xFFFFu);
+        }
+    }
+    if (threadIdx.x < kLanes) {
+        int c = g * kLanes + threadIdx.x;
+        if (c < rd.C) rd.fam[0][c] = c < rd.R ? c : 0;
+    }
+}
+
+// ------------------------------------------------------------------ step begin
+
+__global__ void k_begin(const RunDesc *runs) {
+    const RunDesc &rd = runs[blockIdx.x];
+    RunState *st = rd.st;
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        ok = st->err == 0;
+        const int i = st->step + 1;
+        if (ok && i > rd.max_steps) {
+            st->err = PA_ERR_DONE;
+            st->err_step = i;
+            ok = 0;
+        }
+        if (ok) {
+            double b0 = rd.betas[i - 1], b1 = rd.betas[i];
+            if (!(b1 >= b0) || !(b1 <= 1e300)) {
+                st->err = PA_ERR_ARG;
+                st->err_step = i;
+                ok = 0;
+            } else {
+                bool amb = false;
+                st->t4 = metropolis_threshold(b1, 4, &amb);
+                st->t8 = metropolis_threshold(b1, 8, &amb);
+                if (amb) {
+                    st->err = PA_ERR_NUMERIC;
+                    st->err_step = i;
+                    ok = 0;
+                }
+            }
+        }
+        st->kmin = INT_MAX;
+        st->kmax = -1;
+        st->sum_cnt2 = 0;
+        st->w_total = 0;
+    }
+    __syncthreads();
+    if (!ok) return;
+    for (int k = threadIdx.x; k < rd.K; k += blockDim.x) rd.hist[k] = 0;
+}
+
+// Clear the histogram outside a step (overlap / features of the current population).
+__global__ void k_hist_clear(const RunDesc *runs) {
+    const RunDesc &rd = runs[blockIdx.x];
+    if (threadIdx.x == 0) {
+        rd.st->kmin = INT_MAX;
+        rd.st->kmax = -1;
+    }
+    for (int k = threadIdx.x; k < rd.K; k += blockDim.x) rd.hist[k] = 0;
+}
+
+// n_k = #{j < R_{i-1} : E_j = -2N + 4k}; k_min, k_max of the occupied levels.
+__global__ void k_hist(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err) return;
+    const int Rp = st->R_cur;
+    int kmin = INT_MAX, kmax = -1;
+    const int j0 = b * kSlotBlock, j1 = min(j0 + kSlotBlock, Rp);
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
+        int k = (rd.E[j] + 2 * rd.N) >> 2;
+        atomicAdd(&rd.hist[k], 1);
+        kmin = min(kmin, k);
+        kmax = max(kmax, k);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        kmin = min(kmin, __shfl_xor(kmin, o, 64));
+        kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && kmax >= 0) {
+        atomicMin(&st->kmin, kmin);
+        atomicMax(&st->kmax, kmax);
+    }
+}
+
+// ------------------------------------------------------------------ normalisation
+
+// One block per run.  With dB = beta_i - beta_{i-1} (exact, double-double)
+// and w_l = exp(-4 dB l) the Boltzmann factor of level kmin + l relative to
+// the lowest occupied energy E_min:
+//   S = sum_l n_l w_l,   ln Q_i = -dB E_min + ln(S / R_{i-1})          (Eq. Q)
+//   nearest:     Z_l = ceil(2^32 R w_l / S) = ceil(2^32 tau_hat)      (Eq. taus)
+//   multinomial: q_l = floor(2^40 w_l)
+// Z_l and q_l are the exact integers of the real-valued definitions: they are
+// computed in double-double and a value within the error margin of an integer
+// boundary aborts the run with PA_ERR_NUMERIC.  dB = 0 or a single occupied
+// level make every w_l = 1 and S = R_{i-1} exactly; those use integer math.
+__global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
+    const RunDesc &rd = runs[blockIdx.x];
+    RunState *st = rd.st;
+    if (st->err) return;
+    __shared__ double sh_hi[256], sh_lo[256];
+    __shared__ int amb_any;
+    const int i = st->step + 1;
+    const int Rp = st->R_cur, kmin = st->kmin, kmax = st->kmax;
+    const int nlev = kmax - kmin + 1;
+    const dd db = two_sum(rd.betas[i], -rd.betas[i - 1]);
+    const bool exact = (db.hi == 0.0) || (nlev == 1);
+    if (threadIdx.x == 0) amb_any = 0;
+    dd part{0.0, 0.0};
+    for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
+        dd w{1.0, 0.0};
+        if (!exact && l > 0) dd_exp_neg(dd_mul_d(db, 4.0 * l), &w);
+        rd.wlev[2 * l] = w.hi;
+        rd.wlev[2 * l + 1] = w.lo;
+        int n = rd.hist[kmin + l];
+        if (n) part = dd_add(part, dd_mul_d(w, (double)n));
+    }
+    sh_hi[threadIdx.x] = part.hi;
+    sh_lo[threadIdx.x] = part.lo;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            dd a{sh_hi[threadIdx.x], sh_lo[threadIdx.x]};
+            dd b{sh_hi[threadIdx.x + s], sh_lo[threadIdx.x + s]};
+            dd c = dd_add(a, b);
+            sh_hi[threadIdx.x] = c.hi;
+            sh_lo[threadIdx.x] = c.lo;
+        }
+        __syncthreads();
+    }
+    const dd S{sh_hi[0], sh_lo[0]};
+    if (threadIdx.x == 0) {
+        const double e_min = -2.0 * rd.N + 4.0 * kmin;
+        dd lnq;
+        if (exact && db.hi == 0.0) {
+            lnq = dd{0.0, 0.0};
+        } else {
+            dd a = dd_mul_d(db, -e_min);
+            lnq = dd_add(a, dd_log(dd_div_d(S, (double)Rp)));
+        }
+        st->lnq_hi = lnq.hi;
+        st->lnq_lo = lnq.lo;
+    }
+    bool amb = false;
+    const double R2_32 = ldexp((double)rd.R, 32);
+    for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
+        uint64_t z;
+        if (rd.resample == PA_RESAMPLE_MULTINOMIAL) {
+            if (exact || l == 0) {
+                z = 1ull << 40;
+            } else {
+                dd w{rd.wlev[2 * l], rd.wlev[2 * l + 1]};
+                z = (w.hi == 0.0) ? 0ull : dd_floor_decided(dd_ldexp(w, 40), &amb);
+            }
+        } else {
+            if (exact) {  // tau_hat = R / R_{i-1} exactly
+                unsigned __int128 num = ((unsigned __int128)(uint64_t)rd.R << 32) + (uint64_t)(Rp - 1);
+                z = (uint64_t)(num / (uint64_t)Rp);
+            } else {
+                dd w{rd.wlev[2 * l], rd.wlev[2 * l + 1]};
+                if (w.hi == 0.0) {
+                    z = 1;  // 0 < tau_hat < 2^-900
+                } else {
+                    z = dd_ceil_decided(dd_div(dd_mul_d(w, R2_32), S), &amb);
+                }
+            }
+        }
+        rd.zlev[l] = z;
+    }
+    if (amb) atomicOr(&amb_any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0 && amb_any) {
+        st->err = PA_ERR_NUMERIC;
+        st->err_step = i;
+    }
+}
+
+// ------------------------------------------------------------------ copy counts
+
+// Block partials of the copy counts, then in the last block: exclusive scan of
+// the partials (bases for k_offsets), R_i and sum r_j^2.  part[b*8 + 0..2] =
+// {sum r, sum r^2, base}.
+__device__ void count_partials_tail(const RunDesc &rd, RunState *st, int b, int64_t s,
+                                    int64_t s2) {
+    __shared__ int64_t sh[32];
+    int64_t bs = block_sum_i64(s, sh);
+    int64_t bs2 = block_sum_i64(s2, sh);
+    if (threadIdx.x == 0) {
+        rd.part[b * 8 + 0] = bs;
+        rd.part[b * 8 + 1] = bs2;
+    }
+    if (!last_block(&st->ticket[0], (uint32_t)rd.nblk)) return;
+    if (threadIdx.x == 0) {
+        int64_t run = 0, sq = 0;
+        for (int k = 0; k < rd.nblk; ++k) {
+            rd.part[k * 8 + 2] = run;
+            run += rd.part[k * 8 + 0];
+            sq += rd.part[k * 8 + 1];
+        }
+        if (run > rd.C) {
+            st->err = PA_ERR_CAPACITY;
+            st->err_step = st->step + 1;
+        } else {
+            st->R_new = (int32_t)run;
+            st->sum_cnt2 = sq;
+        }
+    }
+}
+
+// Nearest-integer rule (Eq. resampling-factors, strict "<"): with
+// Z = ceil(2^32 tau_hat) and the parent's uniform u32 (RESAMPLE stream),
+// r_j = floor(tau_hat) + [u32 < 2^32 frac(tau_hat)] = ceil((Z - u32) / 2^32).
+// PA_RESAMPLE_NONE runs get r_j = 1.
+__global__ void __launch_bounds__(256) k_counts_nearest(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err || rd.resample == PA_RESAMPLE_MULTINOMIAL) return;
+    const int Rp = st->R_cur, i = st->step + 1, kmin = st->kmin;
+    const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
+    int64_t s = 0, s2 = 0;
+    if (j < Rp) {
+        uint32_t u[4] = {0, 0, 0, 0};
+        if (rd.resample == PA_RESAMPLE_NEAREST) {
+            U4 x = philox(rd.key0, rd.key1, (uint32_t)(j >> 2), (uint32_t)i, 0u, kTagResample);
+            u[0] = x.x; u[1] = x.y; u[2] = x.z; u[3] = x.w;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            int jj = j + m;
+            if (jj >= Rp) break;
+            int c = 1;
+            if (rd.resample == PA_RESAMPLE_NEAREST) {
+                uint64_t z = rd.zlev[((rd.E[jj] + 2 * rd.N) >> 2) - kmin];
+                c = (int)((z + 0xFFFFFFFFull - u[m]) >> 32);
+            }
+            rd.cnt[jj] = c;
+            s += c;
+            s2 += (int64_t)c * c;
+        }
+    }
+    count_partials_tail(rd, st, b, s, s2);
+}
+
+// Multinomial, pass 1: quantised weight q_j of each parent (into cum[j]),
+// zeroed counts, block sums of q; the last block scans them into bases and W.
+__global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    __shared__ int64_t sh[32];
+    const int Rp = st->R_cur, kmin = st->kmin;
+    int64_t s = 0;
+    for (int j = b * kSlotBlock + (int)threadIdx.x; j < min((b + 1) * kSlotBlock, Rp);
+         j += blockDim.x) {
+        uint64_t q = rd.zlev[((rd.E[j] + 2 * rd.N) >> 2) - kmin];
+        rd.cum[j] = q;
+        rd.cnt[j] = 0;
+        s += (int64_t)q;
+    }
+    int64_t bs = block_sum_i64(s, sh);
+    if (threadIdx.x == 0) rd.part[b * 8 + 3] = bs;
+    if (!last_block(&st->ticket[2], (uint32_t)rd.nblk)) return;
+    if (threadIdx.x == 0) {
+        uint64_t run = 0;
+        for (int k = 0; k < rd.nblk; ++k) {
+            uint64_t t = (uint64_t)rd.part[k * 8 + 3];
+            rd.part[k * 8 + 4] = (int64_t)run;
+            run += t;
+        }
+        st->w_total = run;
+    }
+}
+
+// Multinomial, pass 2: inclusive prefix of q_j -> cum[j].
+__global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    __shared__ int64_t sh[32];
+    const int Rp = st->R_cur;
+    const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
+    uint64_t q[4] = {0, 0, 0, 0};
+    for (int m = 0; m < 4; ++m)
+        if (j + m < Rp) q[m] = rd.cum[j + m];
+    int64_t tot;
+    uint64_t pre = (uint64_t)block_exclusive_scan((int64_t)(q[0] + q[1] + q[2] + q[3]), sh, &tot);
+    uint64_t run = (uint64_t)rd.part[b * 8 + 4] + pre;
+    for (int m = 0; m < 4; ++m) {
+        run += q[m];
+        if (j + m < Rp) rd.cum[j + m] = run;
+    }
+}
+
+// Multinomial, pass 3: draw d (of R) picks the first parent with
+// cum > floor(U64_d * W / 2^64); counts accumulate atomically (order-free).
+__global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    const int Rp = st->R_cur, i = st->step + 1;
+    const uint64_t W = st->w_total;
+    const int d0 = b * kSlotBlock + 4 * (int)threadIdx.x;
+    for (int h = 0; h < 2; ++h) {
+        int d = d0 + 2 * h;
+        if (d >= rd.R) break;
+        U4 x = philox(rd.key0, rd.key1, (uint32_t)(d >> 1), (uint32_t)i, 0u, kTagMulti);
+        uint64_t U[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
+        for (int m = 0; m < 2; ++m) {
+            if (d + m >= rd.R) break;
+            uint64_t target = mulhi64(U[m], W);
+            int lo = 0, hi = Rp - 1;  // first j with cum[j] > target
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (rd.cum[mid] > target) hi = mid; else lo = mid + 1;
+            }
+            atomicAdd(&rd.cnt[lo], 1);
+        }
+    }
+}
+
+// Multinomial, pass 4: block partials of the counts (same tail as nearest).
+__global__ void __launch_bounds__(256) k_count_partials(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    const int Rp = st->R_cur;
+    int64_t s = 0, s2 = 0;
+    for (int j = b * kSlotBlock + (int)threadIdx.x; j < min((b + 1) * kSlotBlock, Rp);
+         j += blockDim.x) {
+        int64_t c = rd.cnt[j];
+        s += c;
+        s2 += c * c;
+    }
+    count_partials_tail(rd, st, b, s, s2);
+}
+
+// off[j] = sum_{l<j} r_l (children of parent j occupy [off[j], off[j] + r_j)),
+// off[R_{i-1}] = R_i.
+__global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err) return;
+    __shared__ int64_t sh[32];
+    const int Rp = st->R_cur;
+    const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
+    int c[4] = {0, 0, 0, 0};
+    for (int m = 0; m < 4; ++m)
+        if (j + m < Rp) c[m] = rd.cnt[j + m];
+    int64_t tot;
+    int64_t pre = block_exclusive_scan(c[0] + c[1] + c[2] + c[3], sh, &tot);
+    int64_t run = rd.part[b * 8 + 2] + pre;
+    for (int m = 0; m < 4; ++m) {
+        if (j + m < Rp) rd.off[j + m] = (int32_t)run;
+        run += c[m];
+    }
+    if (b == 0 && threadIdx.x == 0) rd.off[Rp] = st->R_new;
+}
+
+// ------------------------------------------------------------------ copy / compaction
+
+// Children c of destination group gd take the spins and family label of
+// parent p(c) = the last j with off[j] <= c; parents stay in ascending order,
+// so the copies of one parent are adjacent (tree order).
+__global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map) {
+    int gd;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &gd)];
+    RunState *st = rd.st;
+    if (st->err) return;
+    const int Rn = st->R_new, Rp = st->R_cur;
+    if (gd * kLanes >= Rn) return;
+    const int cur = st->cur, nb = cur ^ 1, N = rd.N;
+    __shared__ int par[kLanes];
+    if (threadIdx.x < kLanes) {
+        int c = gd * kLanes + threadIdx.x;
+        int p = -1;
+        if (c < Rn) {
+            int lo = 0, hi = Rp;  // off[0..Rp] is non-decreasing, off[0] = 0 <= c < off[Rp]
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (rd.off[mid] <= c) lo = mid; else hi = mid - 1;
+            }
+            p = lo;
+        }
+        par[threadIdx.x] = p;
+        if (c < rd.C) rd.fam[nb][c] = p >= 0 ? rd.fam[cur][p] : 0;
+    }
+    __syncthreads();
+    if (rd.layout == PA_LAYOUT_MSC64) {
+        const uint64_t *src = rd.ms[cur];
+        uint64_t *dst = rd.ms[nb] + (size_t)gd * N;
+        for (int site = threadIdx.x; site < N; site += blockDim.x) {
+            uint64_t w = 0;
+            for (int l = 0; l < kLanes; ++l) {
+                int p = par[l];
+                if (p < 0) break;
+                uint64_t v = src[(size_t)(p >> 6) * N + site];
+                w |= ((v >> (p & 63)) & 1ull) << l;
+            }
+            dst[site] = w;
+        }
+    } else {
+        const int8_t *src = rd.s8[cur];
+        uint32_t *dst = reinterpret_cast<uint32_t *>(rd.s8[nb] + (size_t)gd * N * kLanes);
+        for (int it = threadIdx.x; it < N * 16; it += blockDim.x) {
+            int site = it >> 4, q = it & 15;
+            uint32_t word = 0;
+            for (int m = 0; m < 4; ++m) {
+                int p = par[4 * q + m];
+                uint32_t byte = 0xFFu;
+                if (p >= 0) byte = (uint8_t)src[((size_t)(p >> 6) * N + site) * kLanes + (p & 63)];
+                word |= byte << (8 * m);
+            }
+            dst[it] = word;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ Metropolis sweeps
+
+// Bit-sliced Metropolis decision for one word: 64 replicas of one site.  With
+// a_k = s XOR n_k (antiparallel neighbours), A = sum a_k and dE = 8 - 4A:
+// A >= 2 (dE <= 0) always flips; A = 1 (dE = 4) and A = 0 (dE = 8) flip iff
+// u32 < t4 / t8.  u32 is compared bit plane by bit plane from the most
+// significant one, generating planes only while some lane is still tied with
+// its threshold; this equals the full 32-bit comparison.
+__device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, uint64_t a3,
+                                                    uint64_t a4, uint64_t valid, uint64_t t4,
+                                                    uint64_t t8, bool all4, bool all8,
+                                                    uint32_t k0, uint32_t k1, uint32_t w,
+                                                    uint32_t g, uint32_t h) {
+    const uint64_t x12 = a1 ^ a2, y12 = a1 & a2, x34 = a3 ^ a4, y34 = a3 & a4;
+    const uint64_t ge2 = y12 | y34 | (x12 & x34);
+    const uint64_t any = x12 | y12 | x34 | y34;
+    uint64_t eq1 = any & ~ge2;
+    uint64_t eq0 = ~any;
+    uint64_t flip = ge2;
+    if (all4) { flip |= eq1; eq1 = 0; }
+    if (all8) { flip |= eq0; eq0 = 0; }
+    flip &= valid;
+    eq1 &= valid;
+    eq0 &= valid;
+    uint64_t und = eq1 | eq0;
+    const uint32_t T4 = (uint32_t)t4, T8 = (uint32_t)t8;
+    for (uint32_t p = 0; und != 0 && p < 16; ++p) {
+        U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
+        const uint64_t pa = ((uint64_t)x.y << 32) | x.x;
+        const uint64_t pb = ((uint64_t)x.w << 32) | x.z;
+        const uint32_t sa = 31u - 2u * p, sb = 30u - 2u * p;
+        uint64_t t = (((T4 >> sa) & 1u) ? eq1 : 0ull) | (((T8 >> sa) & 1u) ? eq0 : 0ull);
+        flip |= und & ~pa & t;
+        und &= ~(pa ^ t);
+        t = (((T4 >> sb) & 1u) ? eq1 : 0ull) | (((T8 >> sb) & 1u) ? eq0 : 0ull);
+        flip |= und & ~pb & t;
+        und &= ~(pb ^ t);
+    }
+    return flip;
+}
+
+// One block per (run, group): the group's L x L x 64 lattice lives in LDS as
+// N words for all theta sweeps (colour 0 then colour 1; a site's index within
+// its colour w = y L/2 + floor(x/2) and the global half-sweep index
+// h = 2 (theta (i-1) + sweep) + colour key its random planes).  Afterwards
+// each replica's E = 2U - 2N (U antiparallel bonds) and M are measured.
+// With init != 0 no sweep is done (measurement of the beta_0 population).
+template <int LAYOUT>
+__global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map, int init) {
+    extern __shared__ uint64_t lat[];
+    __shared__ int32_t red_u[kLanes], red_up[kLanes];
+    int g;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &g)];
+    RunState *st = rd.st;
+    if (rd.layout != LAYOUT || st->err) return;
+    const int Rn = st->R_new;
+    if (g * kLanes >= Rn) return;
+    const int L = rd.L, N = rd.N, half = L >> 1, nb = st->cur ^ 1;
+    const uint64_t valid = lane_mask(Rn - g * kLanes);
+    const int tid = threadIdx.x, nt = blockDim.x;
+
+    if (LAYOUT == PA_LAYOUT_MSC64) {
+        const uint64_t *src = rd.ms[nb] + (size_t)g * N;
+        for (int w = tid; w < N; w += nt) lat[w] = src[w];
+    } else {
+        const uint4 *src = reinterpret_cast<const uint4 *>(rd.s8[nb] + (size_t)g * N * kLanes);
+        uint16_t *l16 = reinterpret_cast<uint16_t *>(lat);
+        for (int it = tid; it < N * 4; it += nt) l16[it] = (uint16_t)pack16(src[it]);
+    }
+    if (tid < kLanes) {
+        red_u[tid] = 0;
+        red_up[tid] = 0;
+    }
+    __syncthreads();
+
+    const int theta = init ? 0 : rd.theta;
+    const int i = st->step + 1;
+    const uint64_t t4 = st->t4, t8 = st->t8;
+    const bool all4 = t4 >= (1ull << 32), all8 = t8 >= (1ull << 32);
+    const float inv_half = 1.0f / (float)half;
+    for (int s = 0; s < theta; ++s) {
+        for (int colour = 0; colour < 2; ++colour) {
+            const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
+            for (int wi = tid; wi < (N >> 1); wi += nt) {
+                int y = (int)((float)wi * inv_half);
+                int xh = wi - y * half;
+                if (xh >= half) { ++y; xh -= half; }
+                if (xh < 0) { --y; xh += half; }
+                const int x = 2 * xh + ((colour + y) & 1);
+                const int row = y * L;
+                const int up = (y == 0) ? N - L : row - L;
+                const int dn = (y == L - 1) ? 0 : row + L;
+                const int xl = (x == 0) ? L - 1 : x - 1;
+                const int xr = (x == L - 1) ? 0 : x + 1;
+                const uint64_t s0 = lat[row + x];
+                const uint64_t f = metropolis_word(s0 ^ lat[row + xr], s0 ^ lat[row + xl],
+                                                   s0 ^ lat[up + x], s0 ^ lat[dn + x], valid, t4,
+                                                   t8, all4, all8, rd.key0, rd.key1,
+                                                   (uint32_t)wi, (uint32_t)g, h);
+                lat[row + x] = s0 ^ f;
+            }
+            __syncthreads();
+        }
+    }
+
+    // measurement: lane = replica; waves split the rows
+    {
+        const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+        int U = 0, upc = 0;
+        for (int y = wave; y < L; y += nw) {
+            const int row = y * L, dn = (y == L - 1) ? 0 : row + L;
+            for (int x = 0; x < L; ++x) {
+                const uint64_t w0 = lat[row + x];
+                const uint64_t wr = lat[row + ((x == L - 1) ? 0 : x + 1)];
+                const uint64_t wd = lat[dn + x];
+                U += (int)(((w0 ^ wr) >> lane) & 1ull) + (int)(((w0 ^ wd) >> lane) & 1ull);
+                upc += (int)((w0 >> lane) & 1ull);
+            }
+        }
+        atomicAdd(&red_u[lane], U);
+        atomicAdd(&red_up[lane], upc);
+    }
+    __syncthreads();
+    if (tid < kLanes) {
+        const int c = g * kLanes + tid;
+        if (c < Rn) {
+            rd.E[c] = 2 * red_u[tid] - 2 * N;
+            rd.M[c] = 2 * red_up[tid] - N;
+        }
+    }
+    if (theta > 0) {
+        if (LAYOUT == PA_LAYOUT_MSC64) {
+            uint64_t *dst = rd.ms[nb] + (size_t)g * N;
+            for (int w = tid; w < N; w += nt) dst[w] = lat[w];
+        } else {
+            uint4 *dst = reinterpret_cast<uint4 *>(rd.s8[nb] + (size_t)g * N * kLanes);
+            const uint16_t *l16 = reinterpret_cast<const uint16_t *>(lat);
+            for (int it = tid; it < N * 4; it += nt) dst[it] = unpack16(l16[it]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ reduction + record
+
+// Population sums over R_i replicas and family statistics from the tree-ordered
+// labels (families are contiguous runs: a run ending at slot c has length
+// c - first(c) + 1, first(c) found by binary search); the last block writes
+// record i (Sec. "Model and observables" with N -> R_i; Eqs. rhot, rhos,
+// one-step-Reff) and makes the new population current.
+__global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err) return;
+    __shared__ int64_t sh[32];
+    __shared__ double shd[32];
+    const int Rn = st->R_new, nb = st->cur ^ 1;
+    const int32_t *fam = rd.fam[nb];
+    int64_t sE = 0, sE2 = 0, sM = 0, sM2 = 0, f = 0, s2 = 0;
+    double cl = 0.0;
+    for (int c = b * kSlotBlock + (int)threadIdx.x; c < min((b + 1) * kSlotBlock, Rn);
+         c += blockDim.x) {
+        int64_t e = rd.E[c], m = rd.M[c];
+        sE += e;
+        sE2 += e * e;
+        sM += m < 0 ? -m : m;
+        sM2 += m * m;
+        int fc = fam[c];
+        if (c == Rn - 1 || fam[c + 1] != fc) {
+            int lo = 0, hi = c;  // first slot with fam == fc
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (fam[mid] < fc) lo = mid + 1; else hi = mid;
+            }
+            int64_t len = c - lo + 1;
+            f += 1;
+            s2 += len * len;
+            cl += (double)len * log((double)len);
+        }
+    }
+    int64_t v[6] = {sE, sE2, sM, sM2, f, s2};
+    for (int k = 0; k < 6; ++k) {
+        int64_t t = block_sum_i64(v[k], sh);
+        if (threadIdx.x == 0) rd.part[b * 8 + k] = t;
+    }
+    double tcl = block_sum_f64(cl, shd);
+    if (threadIdx.x == 0) rd.partd[b * 2] = tcl;
+    if (!last_block(&st->ticket[1], (uint32_t)rd.nblk)) return;
+    if (threadIdx.x != 0) return;
+    int64_t T[6] = {0, 0, 0, 0, 0, 0};
+    double TCL = 0.0;
+    for (int k = 0; k < rd.nblk; ++k) {
+        for (int q = 0; q < 6; ++q) T[q] += rd.part[k * 8 + q];
+        TCL += rd.partd[k * 2];
+    }
+    const int step = st->step + 1;
+    const double beta = rd.betas[step];
+    if (step > 0) {  // -beta_i F_i = -beta_{i-1} F_{i-1} + ln Q_i, now that step i is complete
+        dd acc = dd_add(dd{st->acc_hi, st->acc_lo}, dd{st->lnq_hi, st->lnq_lo});
+        st->acc_hi = acc.hi;
+        st->acc_lo = acc.lo;
+    }
+    const double N = (double)rd.N, R = (double)Rn;
+    pa_obs o;
+    o.step = step;
+    o.R_i = Rn;
+    o.beta = beta;
+    o.sum_E = T[0];
+    o.sum_E2 = T[1];
+    o.sum_absM = T[2];
+    o.sum_M2 = T[3];
+    const __int128 varE = (__int128)Rn * T[1] - (__int128)T[0] * T[0];
+    const __int128 varM = (__int128)Rn * T[3] - (__int128)T[2] * T[2];
+    o.e = (double)T[0] / (N * R);
+    o.c_v = beta * beta * (double)varE / (N * R * R);
+    o.m = (double)T[2] / (N * R);
+    o.chi = beta * (double)varM / (N * R * R);
+    o.ln_Q = step == 0 ? 0.0 : st->lnq_hi + st->lnq_lo;
+    o.minus_beta_F = st->acc_hi + st->acc_lo;
+    o.n_families = T[4];
+    o.sum_fam2 = T[5];
+    o.sum_cnt2 = step == 0 ? 0 : st->sum_cnt2;
+    o.rho_t = (double)T[5] / R;
+    o.rho_s = exp(TCL / R);
+    o.rho_t_step = step == 0 ? 0.0 : (double)st->sum_cnt2 / R;
+    rd.records[step] = o;
+    st->r_parents = step == 0 ? 0 : st->R_cur;
+    st->step = step;
+    st->cur = nb;
+    st->R_cur = Rn;
+}
+
+// ------------------------------------------------------------------ host access
+
+// Current population of group g -> stage[l * N + site] as int8 +1 / -1.
+__global__ void k_unpack_group(const RunDesc *runs, int r, int g) {
+    const RunDesc &rd = runs[r];
+    const int N = rd.N, cur = rd.st->cur;
+    for (int idx = threadIdx.x + blockIdx.x * blockDim.x; idx < kLanes * N;
+         idx += blockDim.x * gridDim.x) {
+        const int l = idx / N, site = idx - l * N;
+        int up;
+        if (rd.layout == PA_LAYOUT_MSC64)
+            up = (int)((rd.ms[cur][(size_t)g * N + site] >> l) & 1ull);
+        else
+            up = rd.s8[cur][((size_t)g * N + site) * kLanes + l] > 0;
+        rd.stage[idx] = up ? 1 : -1;
+    }
+}
+
+// stage[l * N + site] (int8 +1 / -1, lanes >= n_valid ignored) -> group g of buffer buf.
+__global__ void k_pack_group(const RunDesc *runs, int r, int g, int buf, int n_valid) {
+    const RunDesc &rd = runs[r];
+    const int N = rd.N;
+    for (int site = threadIdx.x + blockIdx.x * blockDim.x; site < N;
+         site += blockDim.x * gridDim.x) {
+        uint64_t w = 0;
+        for (int l = 0; l < n_valid; ++l) w |= (uint64_t)(rd.stage[l * N + site] > 0) << l;
+        size_t o = (size_t)g * N + site;
+        if (rd.layout == PA_LAYOUT_MSC64) {
+            rd.ms[buf][o] = w;
+        } else {
+            uint4 *dst = reinterpret_cast<uint4 *>(rd.s8[buf] + o * kLanes);
+            for (int q = 0; q < 4; ++q) dst[q] = unpack16((uint32_t)(w >> (16 * q)) & 0xFFFFu);
+        }
+    }
+}
+
+// Adopt a population written into buffer 0 (R_i replicas) as the current one.
+__global__ void k_adopt_begin(const RunDesc *runs, int r, int R_i) {
+    RunState *st = runs[r].st;
+    st->err = 0;
+    st->cur = 1;
+    st->R_new = R_i;
+}
+__global__ void k_adopt_end(const RunDesc *runs, int r, int step, double acc) {
+    RunState *st = runs[r].st;
+    st->step = step;
+    st->cur = 0;
+    st->R_cur = st->R_new;
+    st->acc_hi = acc;
+    st->acc_lo = 0.0;
+}
+
+__global__ void k_set_beta(const RunDesc *runs, int r, int idx, double beta) {
+    const RunDesc &rd = runs[r];
+    if (idx >= 0 && idx <= rd.max_steps) rd.betas[idx] = beta;
+}
+
+// ------------------------------------------------------------------ overlap / adaptive step
+
+// mode 0: alpha at dbeta; mode 1: bisection for alpha(dbeta) = target on (0, dbeta].
+__global__ void __launch_bounds__(256) k_overlap(const RunDesc *runs, int r, double dbeta,
+                                                 double target, int mode) {
+    const RunDesc &rd = runs[r];
+    RunState *st = rd.st;
+    __shared__ double shd[32];
+    const int kmin = st->kmin, nlev = st->kmax - st->kmin + 1, R = st->R_cur;
+    if (mode == 0) {
+        double a = overlap_block(rd, kmin, nlev, R, dbeta, shd);
+        if (threadIdx.x == 0) st->alpha_out = a;
+        return;
+    }
+    double hi = dbeta;
+    double ahi = overlap_block(rd, kmin, nlev, R, hi, shd);
+    if (ahi >= target) {
+        if (threadIdx.x == 0) { st->dbeta_out = hi; st->alpha_out = ahi; }
+        return;
+    }
+    double lo = 0.0, alo = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double mid = 0.5 * (lo + hi);
+        double am = overlap_block(rd, kmin, nlev, R, mid, shd);
+        if (am >= target) { lo = mid; alo = am; } else { hi = mid; }
+    }
+    if (threadIdx.x == 0) { st->dbeta_out = lo; st->alpha_out = alo; }
+}
+
+// ------------------------------------------------------------------ workspace clear
+
+__global__ void k_fill_zero(uint4 *p, size_t n16) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n16;
+         k += (size_t)blockDim.x * gridDim.x)
+        p[k] = uint4{0u, 0u, 0u, 0u};
+}
+
+// ------------------------------------------------------------------ raw Philox
+
+__global__ void k_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, int64_t n,
+                         uint32_t *out) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)blockDim.x * gridDim.x) {
+        U4 x = philox(k0, k1, ctr[4 * t], ctr[4 * t + 1], ctr[4 * t + 2], ctr[4 * t + 3]);
+        out[4 * t] = x.x;
+        out[4 * t + 1] = x.y;
+        out[4 * t + 2] = x.z;
+        out[4 * t + 3] = x.w;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+#define PA_LAUNCH(...)                                   \
+    do {                                                 \
+        hipLaunchKernelGGL(__VA_ARGS__);                 \
+        hipError_t e_ = hipGetLastError();               \
+        if (e_ != hipSuccess) return e_;                 \
+    } while (0)
+
+hipError_t launch_init(const LaunchCtx &c) {
+    PA_LAUNCH(k_init_population, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs,
+              c.groups.map);
+    return hipSuccess;
+}
+
+hipError_t launch_sweeps(const LaunchCtx &c, int init) {
+    for (const auto &cls : c.sweep_classes) {
+        size_t lds = (size_t)cls.N * sizeof(uint64_t);
+        if (cls.has_msc)
+            PA_LAUNCH(k_sweep<PA_LAYOUT_MSC64>, dim3(cls.total), dim3(c.sweep_threads), lds,
+                      c.stream, c.runs, cls.map, init);
+        if (cls.has_int8)
+            PA_LAUNCH(k_sweep<PA_LAYOUT_INT8>, dim3(cls.total), dim3(c.sweep_threads), lds,
+                      c.stream, c.runs, cls.map, init);
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_reduce(const LaunchCtx &c) {
+    PA_LAUNCH(k_reduce, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+    return hipSuccess;
+}
+
+hipError_t launch_step(const LaunchCtx &c) {
+    PA_LAUNCH(k_begin, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
+    PA_LAUNCH(k_hist, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+    PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
+    if (c.any_nearest)
+        PA_LAUNCH(k_counts_nearest, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
+                  c.slots.map);
+    if (c.any_multi) {
+        PA_LAUNCH(k_multi_weights, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
+                  c.slots.map);
+        PA_LAUNCH(k_multi_cum, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
+                  c.slots.map);
+        PA_LAUNCH(k_multi_draw, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
+                  c.slots.map);
+        PA_LAUNCH(k_count_partials, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
+                  c.slots.map);
+    }
+    PA_LAUNCH(k_offsets, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+    PA_LAUNCH(k_gather, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
+    hipError_t e = launch_sweeps(c, 0);
+    if (e != hipSuccess) return e;
+    return launch_reduce(c);
+}
+
+hipError_t launch_hist_current(const LaunchCtx &c) {
+    PA_LAUNCH(k_hist_clear, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
+    PA_LAUNCH(k_hist, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+    return hipSuccess;
+}
+
+hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta, double target, int mode) {
+    PA_LAUNCH(k_overlap, dim3(1), dim3(256), 0, c.stream, c.runs, r, dbeta, target, mode);
+    return hipSuccess;
+}
+
+hipError_t launch_set_beta(const LaunchCtx &c, int r, int idx, double beta) {
+    PA_LAUNCH(k_set_beta, dim3(1), dim3(1), 0, c.stream, c.runs, r, idx, beta);
+    return hipSuccess;
+}
+
+hipError_t launch_unpack_group(const LaunchCtx &c, int r, int g, int N) {
+    int blocks = (kLanes * N + 255) / 256;
+    PA_LAUNCH(k_unpack_group, dim3(blocks), dim3(256), 0, c.stream, c.runs, r, g);
+    return hipSuccess;
+}
+
+hipError_t launch_pack_group(const LaunchCtx &c, int r, int g, int buf, int n_valid, int N) {
+    int blocks = (N + 255) / 256;
+    PA_LAUNCH(k_pack_group, dim3(blocks), dim3(256), 0, c.stream, c.runs, r, g, buf, n_valid);
+    return hipSuccess;
+}
+
+hipError_t launch_adopt_begin(const LaunchCtx &c, int r, int R_i) {
+    PA_LAUNCH(k_adopt_begin, dim3(1), dim3(1), 0, c.stream, c.runs, r, R_i);
+    return hipSuccess;
+}
+
+hipError_t launch_adopt_end(const LaunchCtx &c, int r, int step, double acc) {
+    PA_LAUNCH(k_adopt_end, dim3(1), dim3(1), 0, c.stream, c.runs, r, step, acc);
+    return hipSuccess;
+}
+
+hipError_t launch_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, int64_t n, uint32_t *out,
+                         hipStream_t stream) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    PA_LAUNCH(k_philox, dim3((unsigned)blocks), dim3(256), 0, stream, k0, k1, ctr, n, out);
+    return hipSuccess;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
+    const size_t n16 = bytes / 16;  // workspace sizes are multiples of 256 bytes
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    PA_LAUNCH(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, stream, (uint4 *)p, n16);
+    return hipSuccess;
+}
+
+hipError_t configure_kernels() {
+    // the L = 128 lattice (16384 words) needs 128 KiB of LDS per block
+    hipError_t e = hipFuncSetAttribute((const void *)k_sweep<PA_LAYOUT_MSC64>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kMaxL * kMaxL * (int)sizeof(uint64_t));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_sweep<PA_LAYOUT_INT8>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kMaxL * kMaxL * (int)sizeof(uint64_t));
+}
+
+}  // namespace pa

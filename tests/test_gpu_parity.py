@@ -1,0 +1,299 @@
+"""GPU parity: the HIP library (through its C-ABI) against the CPU oracle.
+
+Integer results (spins, copy counts, energies, family labels, population
+sums) must match bit for bit; ln Q and -beta F within 1e-12 relative; the
+other floating-point observables within 1e-12 relative as well (they are
+formed from exact integer sums on both sides).
+"""
+import ctypes
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_2102_06611_amd as pa
+from oracle import pa_oracle as po
+from workloads import PARITY_SEED, linear_schedule
+
+pytestmark = pytest.mark.gpu
+
+INT_FIELDS = ("step", "R_i", "sum_E", "sum_E2", "sum_absM", "sum_M2", "n_families", "sum_fam2",
+              "sum_cnt2")
+FP_FIELDS = ("beta", "e", "c_v", "m", "chi", "ln_Q", "minus_beta_F", "rho_t", "rho_s",
+             "rho_t_step")
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pa.lib()
+
+
+def close(a, b, rel=1e-12):
+    return abs(a - b) <= rel * max(abs(a), abs(b)) or a == b
+
+
+def check_record(got: dict, want, ctx=""):
+    for k in INT_FIELDS:
+        assert got[k] == getattr(want, k), (ctx, k, got[k], getattr(want, k))
+    for k in FP_FIELDS:
+        assert close(got[k], getattr(want, k)), (ctx, k, got[k], getattr(want, k))
+
+
+def check_population(run: "pa.Run", ref: po.OracleRun, ctx=""):
+    spins, fam, E, M = run.population()
+    assert spins.shape == ref.spins.shape, ctx
+    assert np.array_equal(spins, ref.spins), ctx
+    assert np.array_equal(fam, ref.fam), ctx
+    assert np.array_equal(E, ref.E), ctx
+    assert np.array_equal(M, ref.M), ctx
+
+
+def test_philox_device_matches_oracle():
+    rng = np.random.default_rng(0)
+    n = 4096
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:16] = 0
+    ctr[16:32] = 0xFFFFFFFF
+    dev_ctr = torch.from_numpy(ctr.view(np.int32)).cuda()
+    dev_out = torch.zeros_like(dev_ctr)
+    for key in (0, 12345, 2 ** 64 - 1):
+        pa.philox4x32_10(key, dev_ctr, dev_out)
+        torch.cuda.synchronize()
+        out = dev_out.cpu().numpy().view(np.uint32)
+        for k in list(range(64)) + list(rng.integers(0, n, 200)):
+            assert np.array_equal(out[k], po.philox4x32_10(key, ctr[k])), (key, k)
+
+
+@pytest.mark.parametrize("layout", ["msc64", "int8"])
+@pytest.mark.parametrize("L,R", [(8, 200), (6, 64), (4, 1), (12, 130)])
+def test_initial_population_matches_oracle(layout, L, R):
+    log("init", layout, L, R)
+    betas = linear_schedule(0.3, 2)
+    run = pa.Run(L, R, betas, 1, PARITY_SEED, "nearest", layout)
+    ref = po.OracleRun(L, R, 1, PARITY_SEED, "nearest", betas)
+    check_record(run.observables(0), ref.records[0], "record 0")
+    check_population(run, ref, "init")
+    run.close()
+
+
+CASES = [
+    # L, R, theta, n_steps, beta_f, resample, layout
+    (8, 200, 3, 8, 0.44, "nearest", "msc64"),
+    (8, 200, 3, 8, 0.44, "nearest", "int8"),
+    (6, 130, 2, 6, 0.6, "multinomial", "msc64"),
+    (6, 130, 2, 6, 0.6, "multinomial", "int8"),
+    (4, 64, 5, 10, 1.2, "nearest", "msc64"),
+    (10, 1, 2, 5, 0.5, "nearest", "msc64"),
+    (8, 300, 0, 5, 0.8, "nearest", "msc64"),
+    (16, 150, 2, 4, 0.44, "multinomial", "msc64"),
+    (12, 100, 2, 4, 2.0, "none", "int8"),
+]
+
+
+@pytest.mark.parametrize("L,R,theta,n,bf,resample,layout", CASES)
+def test_run_parity_step_by_step(L, R, theta, n, bf, resample, layout):
+    log("run parity", L, R, theta, n, bf, resample, layout)
+    betas = linear_schedule(bf, n)
+    run = pa.Run(L, R, betas, theta, PARITY_SEED, resample, layout)
+    ref = po.OracleRun(L, R, theta, PARITY_SEED, resample, betas)
+    for i in range(1, n + 1):
+        run.anneal_step()
+        ref.anneal_step()
+        check_record(run.observables(i), ref.records[i], "step %d" % i)
+        assert np.array_equal(run.copy_counts(), ref.last_counts), i
+        check_population(run, ref, "step %d" % i)
+    run.close()
+
+
+@pytest.mark.slow
+def test_small_nearest_workload_full_run():
+    """L=8, R=1000, beta 0 -> 0.44 in 101 steps, theta=10, nearest, int8."""
+    L, R, theta, n = 8, 1000, 10, 101
+    betas = linear_schedule(0.44, n)
+    run = pa.Run(L, R, betas, theta, PARITY_SEED, "nearest", "int8")
+    run.run(n)
+    run.sync()
+    ref = po.run(L, R, betas, theta, PARITY_SEED, "nearest")
+    for i in range(n + 1):
+        check_record(run.observables(i), ref.records[i], "step %d" % i)
+    check_population(run, ref, "final")
+    run.close()
+
+
+def test_layouts_give_identical_trajectories():
+    L, R, n = 32, 5000, 10
+    betas = linear_schedule(0.44, n)
+    a = pa.Run(L, R, betas, 4, 7, "nearest", "msc64")
+    b = pa.Run(L, R, betas, 4, 7, "nearest", "int8")
+    a.run(n)
+    b.run(n)
+    for i in range(n + 1):
+        assert a.observables(i) == b.observables(i), i
+    sa, fa, Ea, Ma = a.population()
+    sb, fb, Eb, Mb = b.population()
+    assert np.array_equal(sa, sb) and np.array_equal(fa, fb) and np.array_equal(Ea, Eb)
+
+
+def test_graph_replay_matches_stepping():
+    L, R, n = 16, 3000, 12
+    betas = linear_schedule(0.5, n)
+    s = torch.cuda.Stream()
+    a = pa.Run(L, R, betas, 3, 11, "nearest", "msc64", stream=s)
+    b = pa.Run(L, R, betas, 3, 11, "nearest", "msc64")
+    a.run(n)
+    for _ in range(n):
+        b.anneal_step()
+    a.sync()
+    b.sync()
+    for i in range(n + 1):
+        assert a.observables(i) == b.observables(i), i
+    assert a.get_state() == b.get_state()
+
+
+def test_same_seed_is_bit_identical_and_seed_matters():
+    betas = linear_schedule(0.44, 6)
+    blobs = []
+    for seed in (5, 5, 6):
+        r = pa.Run(16, 700, betas, 3, seed, "multinomial", "msc64")
+        r.run(6)
+        blobs.append(r.get_state())
+        r.close()
+    assert blobs[0] == blobs[1]
+    assert blobs[0] != blobs[2]
+
+
+def test_checkpoint_resume_is_bit_identical():
+    betas = linear_schedule(0.6, 10)
+    a = pa.Run(12, 500, betas, 2, 3, "nearest", "int8")
+    a.run(4)
+    blob = a.get_state()
+    a.run(6)
+    b = pa.Run(12, 500, betas, 2, 3, "nearest", "int8")
+    b.set_state(blob)
+    b.run(6)
+    assert a.get_state() == b.get_state()
+    for i in range(11):
+        assert a.observables(i) == b.observables(i)
+
+
+def test_set_population_resumes_like_the_oracle():
+    L, R, theta = 8, 150, 2
+    betas = linear_schedule(0.5, 6)
+    ref = po.OracleRun(L, R, theta, 9, "nearest", betas)
+    for _ in range(3):
+        ref.anneal_step()
+    run = pa.Run(L, R, betas, theta, 9, "nearest", "msc64")
+    run.set_population(3, ref.spins, ref.fam, ref.minus_beta_F)
+    check_population(run, ref, "adopted")
+    for i in range(4, 7):
+        run.anneal_step()
+        ref.anneal_step()
+        check_record(run.observables(i), ref.records[i], "step %d" % i)
+        check_population(run, ref, "step %d" % i)
+
+
+def test_zero_temperature_step_is_the_identity_before_sweeps():
+    betas = np.array([0.0, 0.0, 0.0])
+    run = pa.Run(8, 256, betas, 0, 4, "nearest", "msc64")
+    s0, f0, _, _ = run.population()
+    run.anneal_step()
+    o = run.observables(1)
+    assert o["ln_Q"] == 0.0 and o["R_i"] == 256
+    assert np.all(run.copy_counts() == 1)
+    s1, f1, _, _ = run.population()
+    assert np.array_equal(s0, s1) and np.array_equal(f0, f1)
+
+
+def test_capacity_overflow_is_reported_and_state_kept():
+    L, R = 8, 128
+    betas = linear_schedule(0.6, 40)
+    run = pa.Run(L, R, betas, 1, 2, "nearest", "msc64", capacity=128)
+    ref = po.OracleRun(L, R, 1, 2, "nearest", betas)
+    for _ in range(40):
+        run.anneal_step()
+    with pytest.raises(pa.PAError) as ei:
+        run.sync()
+    assert ei.value.status == pa.PA_ERR_CAPACITY
+    step, R_i = run.current()
+    # the oracle (no capacity limit) reaches the same population at that step
+    for _ in range(step):
+        ref.anneal_step()
+    assert len(ref.E) == R_i <= 128
+    check_population(run, ref, "kept step %d" % step)
+    ref.anneal_step()
+    assert len(ref.E) > 128  # the step that overflowed
+
+
+def test_schedule_end_is_reported():
+    run = pa.Run(8, 64, linear_schedule(0.3, 2), 1, 1, "nearest", "msc64")
+    run.anneal_step()
+    run.anneal_step()
+    with pytest.raises(pa.PAError) as ei:
+        run.anneal_step()
+    assert ei.value.status == pa.PA_ERR_DONE
+    run.sync()
+
+
+def _sampled_step_parity(L, R, resample, layout, n_steps, beta_f, k, theta, seed, n_groups=6):
+    """GPU step k -> k+1 at full size; the oracle recomputes the copy counts of
+    all parents and the sweeps of a sample of replica groups."""
+    betas = linear_schedule(beta_f, n_steps)
+    s = torch.cuda.Stream()
+    run = pa.Run(L, R, betas, theta, seed, resample, layout, stream=s)
+    run.run(k)
+    run.sync()
+    snap_spins, snap_fam, snap_E, _ = run.population()
+    acc = run.observables(k)["minus_beta_F"]
+    run.anneal_step()
+    got = run.observables(k + 1)
+    counts = run.copy_counts()
+    ref = po.OracleRun(L, 4, theta, seed, resample, betas)  # population replaced below
+    ref.R = R
+    ref.E = snap_E.copy()
+    ref_counts, ln_q = ref.copy_counts(betas[k], betas[k + 1], k + 1)
+    assert np.array_equal(counts, ref_counts)
+    assert got["R_i"] == int(ref_counts.sum())
+    assert close(got["ln_Q"], float(ln_q))
+    assert close(got["minus_beta_F"], acc + float(ln_q), 1e-12)
+    off = np.concatenate([[0], np.cumsum(ref_counts)])
+    R_new = int(off[-1])
+    G = (R_new + 63) // 64
+    rng = np.random.default_rng(seed)
+    groups = sorted(set([0, G - 1] + list(rng.integers(0, G, n_groups))))
+    t4, t8 = po.metropolis_threshold(betas[k + 1], 4), po.metropolis_threshold(betas[k + 1], 8)
+    for g in groups:
+        lo, hi = 64 * g, min(64 * g + 64, R_new)
+        parents = np.searchsorted(off, np.arange(lo, hi), side="right") - 1
+        kids = np.ascontiguousarray(snap_spins[parents])
+        po.sweeps(seed, L, kids, k + 1, theta, t4, t8, slot0=lo)
+        E, M = po.energy_magnetisation(L, kids)
+        gs, gf, gE, gM = run.population(lo, hi - lo)
+        assert np.array_equal(gs, kids), g
+        assert np.array_equal(gf, snap_fam[parents]), g
+        assert np.array_equal(gE, E) and np.array_equal(gM, M), g
+    run.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("layout", ["msc64", "int8"])
+def test_l64_multinomial_sampled_step_parity(layout):
+    """L=64, R=100000, multinomial, beta 0 -> 0.4407 in 200 steps: step 120 -> 121."""
+    log("L64 sampled", layout)
+    _sampled_step_parity(64, 100_000, "multinomial", layout, 200, 0.4407, 120, 10, PARITY_SEED)
+
+
+@pytest.mark.slow
+def test_l128_nearest_sampled_step_parity():
+    """L=128, R=100000, nearest, multispin, beta 0 -> 1.0 in 400 steps: step 180 -> 181."""
+    log("L128 sampled")
+    _sampled_step_parity(128, 100_000, "nearest", "msc64", 400, 1.0, 180, 10, PARITY_SEED, 3)
