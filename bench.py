@@ -1,0 +1,212 @@
+"""Benchmark: population annealing, L = 64, R = 100000, multinomial resampling,
+beta 0 -> 0.4407 in 200 steps, theta = 10 checkerboard Metropolis sweeps.
+
+A step is one whole temperature step of the method on the device: histogram,
+ln Q, copy counts, offsets, copy/compaction, theta sweeps, measurement and
+record.  The timed region runs K consecutive steps of a fresh run with its
+population resident in HBM; value = spin-flip attempts (sum R_i N theta) per
+nanosecond of wall time.  Both layouts are timed; the multispin one is the
+headline.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+L, R, THETA, BETA_F, N_STEPS = 64, 100_000, 10, 0.4407, 200
+SEED = 12345
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: full-rate 32-bit VALU lane-operations per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU issue slots (full-rate lane-ops) of the minimal work, see the design doc:
+SLOTS_PER_PHILOX = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
+SLOTS_PER_PLANE_PAIR = 40  # lazy comparison of two 64-bit planes against the thresholds
+SLOTS_PER_WORD = 24      # neighbour XORs and the bit-sliced A >= 2 / A = 1 / A = 0 classes
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pa_kernels.hip", "pa_device.hpp", "pa_block.hpp"):
+        with open(os.path.join(ROOT, "paper_2102_06611_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """FETCH/WRITE bytes per launch from profiles/traffic.json, if taken on this source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def time_layout(pa, torch, betas, layout, K, W):
+    stream = torch.cuda.Stream()
+    # warmup: W steps of a separate run (compiles nothing; brings clocks and caches up)
+    if W > 0:
+        w = pa.Run(L, R, betas, THETA, SEED + 1, "multinomial", layout, stream=stream)
+        for _ in range(min(W, N_STEPS)):
+            w.anneal_step()
+        w.sync()
+        w.close()
+    run = pa.Run(L, R, betas, THETA, SEED, "multinomial", layout, stream=stream)
+    run.sync()
+    run.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        run.anneal_step()
+    run.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = run.profile_read()
+    recs = [run.observables(i) for i in range(K + 1)]
+    attempts = sum(r["R_i"] for r in recs[1:]) * L * L * THETA
+    return run, wall, prof, recs, attempts
+
+
+def cpu_baseline(betas, energies):
+    """The oracle, single-threaded, on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import pa_oracle as po
+    beta = betas[-1]
+    t4, t8 = po.metropolis_threshold(beta, 4), po.metropolis_threshold(beta, 8)
+    spins = po.init_spins(SEED, L, 64)
+    t0 = time.perf_counter()
+    sweeps = 0
+    while True:  # sweeps of one 64-replica group until >= 8 s of CPU work
+        po.sweeps(SEED, L, spins, N_STEPS, 1, t4, t8)
+        sweeps += 1
+        if time.perf_counter() - t0 > 8.0 or sweeps >= 200:
+            break
+    t_sweep = time.perf_counter() - t0
+    attempts = 64 * L * L * sweeps
+    o = po.OracleRun(L, 4, THETA, SEED, "multinomial", betas)
+    o.R = R
+    o.E = np.asarray(energies, dtype=np.int32)
+    t1 = time.perf_counter()
+    o.copy_counts(betas[100], betas[101], 101)
+    t_res = time.perf_counter() - t1
+    return {"value": attempts / t_sweep / 1e9, "unit": "attempts/ns", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d sweeps of 64 replicas (L=64) at beta=%.4f, plus one multinomial "
+                      "resampling of %d parents (%.2f s)" % (sweeps, beta, len(energies), t_res),
+            "resample_s_per_step": t_res, "sweep_seconds": t_sweep}
+
+
+def head_candidate(layouts: str) -> str:
+    names = layouts.split(",")
+    return "msc64" if "msc64" in names else names[0]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=N_STEPS)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--layouts", default="msc64,int8")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs one population per device and "
+              "uses no collectives; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    K = max(1, min(args.steps, N_STEPS))
+    import numpy as np
+    import torch
+    import paper_2102_06611_amd as pa
+    from workloads import linear_schedule
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    betas = linear_schedule(BETA_F, N_STEPS)
+    exact = json.load(open(os.path.join(ROOT, "tests", "golden", "exact_lnz.json")))
+    lnz = exact["schedules"]["L64_0.4407_200"]["ln_z"]
+
+    results = {}
+    energies_mid = None
+    for layout in args.layouts.split(","):
+        log("timing layout %s: %d steps" % (layout, K))
+        run, wall, prof, recs, attempts = time_layout(pa, torch, betas, layout, K, args.warmup)
+        n = prof["steps"]
+        sweep_ms = prof["ms_sweep"] / n
+        res_ms = prof["ms_resample"] / n
+        meas_ms = prof["ms_measure"] / n
+        words = prof["sweep_words"] / n
+        calls = prof["philox_calls"] / n
+        alg_slots = calls * (SLOTS_PER_PHILOX + SLOTS_PER_PLANE_PAIR) + words * SLOTS_PER_WORD
+        achieved_tops = alg_slots / (sweep_ms * 1e-3) / 1e12
+        group_bytes = (L * L * 8) if layout == "msc64" else (L * L * 64)
+        copy_bytes = 2 * math.ceil(R / 64) * group_bytes  # a5: read parents, write children
+        err = [abs(recs[i]["minus_beta_F"] - lnz[i]) / (L * L) for i in range(K + 1)]
+        results[layout] = {
+            "attempts_per_ns": attempts / wall / 1e9,
+            "sweep_attempts_per_ns": attempts / (prof["ms_sweep"] * 1e-3) / 1e9,
+            "ms_per_step": wall * 1e3 / K,
+            "sweep_ms_per_step": sweep_ms,
+            "resample_us_per_step": res_ms * 1e3,
+            "measure_us_per_step": meas_ms * 1e3,
+            "philox_calls_per_word": calls / words if words else 0.0,
+            "sweep_alu_tops": achieved_tops,
+            "resample_copy_bytes": copy_bytes,
+            "beta_f_error_per_spin": {"at_last_step": err[-1], "max": max(err)},
+            "beta_last": recs[-1]["beta"],
+        }
+        if layout == head_candidate(args.layouts) and not args.no_cpu_baseline:
+            # energies entering step 101, for the CPU-baseline resampling sample
+            e_run = pa.Run(L, R, betas, THETA, SEED, "multinomial", layout)
+            for _ in range(100):
+                e_run.anneal_step()
+            _, _, energies_mid, _ = e_run.population(spins=False)
+            e_run.close()
+        run.close()
+        torch.cuda.empty_cache()
+
+    head_layout = "msc64" if "msc64" in results else list(results)[0]
+    head = results[head_layout]
+    traffic = measured_traffic("k_sweep_msc64")
+    roof = {"bound": "alu", "kernel": "k_sweep<msc64>", "achieved": head["sweep_alu_tops"],
+            "peak": VALU_PEAK_TOPS, "unit": "Tops/s (32-bit VALU lane-ops)",
+            "frac": head["sweep_alu_tops"] / VALU_PEAK_TOPS, "traffic": traffic}
+    out = {
+        "metric": "spin-flip attempts/ns + resample/step (L=64,R=1e5); βF error vs exact",
+        "value": head["attempts_per_ns"], "unit": "attempts/ns", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64 bit-sliced (int32 counts, f64 ln Q)",
+        "data": "synthetic",
+        "config": {"workload": "2D Ising L=64 periodic, R=100000, multinomial resampling, beta 0->0.4407 "
+                               "in 200 steps, theta=10, %s layout" % head_layout,
+                   "L": L, "R": R, "theta": THETA, "n_steps": N_STEPS, "seed": SEED,
+                   "steps_timed": "1..%d" % K},
+        "resample_us_per_step": head["resample_us_per_step"],
+        "roofline": roof,
+        "layouts": results,
+    }
+    if not args.no_cpu_baseline and energies_mid is not None:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(betas, energies_mid)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -136,8 +136,9 @@ pa_status pa_observables(pa_ctx *ctx, int32_t step, pa_obs *out);
 /* Current step index i and population size R_i.  Synchronises. */
 pa_status pa_current(pa_ctx *ctx, int32_t *step, int32_t *R_i);
 
-/* Energy histogram of the population that entered the last resampling:
- * counts[k] = #{j : E_j = -2 L^2 + 4 (k_min + k)}, k < n_bins.  Synchronises. */
+/* Energy histogram of the current population (the one the next step
+ * reweights): counts[k] = #{j : E_j = -2 L^2 + 4 (k_min + k)}, k < n_bins.
+ * Synchronises. */
 pa_status pa_energy_histogram(pa_ctx *ctx, int32_t *counts, int32_t cap, int32_t *k_min,
                               int32_t *n_bins);
 
@@ -176,6 +177,19 @@ pa_status pa_overlap(pa_ctx *ctx, double dbeta, double *alpha);
  * _target, by bisection on the device (dbeta_max if that already qualifies).
  * Synchronises. */
 pa_status pa_adaptive_dbeta(pa_ctx *ctx, double alpha_target, double dbeta_max, double *dbeta);
+
+/* Phase timing.  While enabled, every step records HIP events on the run's
+ * stream before the resampling (histogram, Q_i, copy counts, offsets,
+ * copy/compaction), before the sweeps, before the measurement/record kernel
+ * and after it; the sweep kernel also counts the Philox4x32-10 calls it makes.
+ * pa_profile(ctx, 1) resets the totals.  Asynchronous. */
+pa_status pa_profile(pa_ctx *ctx, int32_t enable);
+
+/* Totals since profiling was enabled: steps timed, summed milliseconds of the
+ * three phases, Philox calls and 64-replica words updated by the sweeps.
+ * Synchronises. */
+pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, double *ms_sweep,
+                          double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words);
 
 /* Release host-side state; NULL-safe; does not free the workspace. */
 void pa_destroy(pa_ctx *ctx);

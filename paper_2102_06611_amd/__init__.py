@@ -103,6 +103,8 @@ SIGNATURES = {
     "pa_anneal_step_adaptive": (_i32, [_vp, _dbl, _dbl]),
     "pa_anneal_step_learned": (_i32, [_vp, _vp, _dbl, _dbl, _dbl]),
     "pa_schedule_log": (_i32, [_vp, _vp, _vp, _P(_i32), _P(_dbl), _i32, _P(_i32)]),
+    "pa_profile": (_i32, [_vp, _i32]),
+    "pa_profile_read": (_i32, [_vp, _P(_i32), _P(_dbl), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64)]),
 }
 
 
@@ -158,6 +160,7 @@ class Run:
         self.L, self.N, self.R = L, L * L, R
         self.cfg, self._betas = make_config(L, R, betas, theta, seed, resample, layout,
                                             capacity, n_steps)
+        self.max_steps = self.cfg.n_steps
         nbytes = ctypes.c_size_t()
         _check(lib().pa_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
         self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
@@ -263,6 +266,19 @@ class Run:
 
     def features(self, dev_feat) -> None:
         _check(lib().pa_features(self.h, ctypes.c_void_p(dev_feat.data_ptr())), self.h)
+
+    def profile(self, enable: bool = True):
+        _check(lib().pa_profile(self.h, 1 if enable else 0), self.h)
+
+    def profile_read(self) -> dict:
+        n = ctypes.c_int32()
+        t = [ctypes.c_double() for _ in range(3)]
+        calls, words = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().pa_profile_read(self.h, ctypes.byref(n), *[ctypes.byref(x) for x in t],
+                                     ctypes.byref(calls), ctypes.byref(words)), self.h)
+        return {"steps": n.value, "ms_resample": t[0].value, "ms_sweep": t[1].value,
+                "ms_measure": t[2].value, "philox_calls": calls.value,
+                "sweep_words": words.value}
 
     def anneal_step_adaptive(self, alpha_target: float, beta_final: float):
         _check(lib().pa_anneal_step_adaptive(self.h, float(alpha_target), float(beta_final)), self.h)

@@ -227,6 +227,10 @@ struct pa_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dead = false;
+    // phase timing (pa_profile)
+    bool profiling = false;
+    std::vector<hipEvent_t> events;  // 4 per profiled step
+    int profiled_steps = 0;
 };
 
 struct pa_ctx {
@@ -335,6 +339,8 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         s.step = -1;
         s.cur = 1;
         s.R_new = p.R;
+        s.kmin = INT32_MAX;  // empty histogram; the first reduction fills it
+        s.kmax = -1;
         dd_n_ln2(p.N, &s.acc_hi, &s.acc_lo);  // ln Z_0 = L^2 ln 2
     }
     PA_HIP(B, launch_fill_zero(B->ws, B->lay.bytes, B->stream));  // deterministic contents
@@ -415,7 +421,24 @@ pa_status engine_sync(pa_batch *B) {
 
 pa_status engine_step(pa_batch *B) {
     if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
-    PA_HIP(B, launch_step(B->lc));
+    if (!B->profiling) {
+        PA_HIP(B, launch_step(B->lc));
+    } else {
+        const size_t base = (size_t)B->profiled_steps * 4;
+        while (B->events.size() < base + 4) {
+            hipEvent_t ev;
+            PA_HIP(B, hipEventCreate(&ev));
+            B->events.push_back(ev);
+        }
+        PA_HIP(B, hipEventRecord(B->events[base], B->stream));
+        PA_HIP(B, launch_resample(B->lc));
+        PA_HIP(B, hipEventRecord(B->events[base + 1], B->stream));
+        PA_HIP(B, launch_sweeps(B->lc, 0));
+        PA_HIP(B, hipEventRecord(B->events[base + 2], B->stream));
+        PA_HIP(B, launch_reduce(B->lc));
+        PA_HIP(B, hipEventRecord(B->events[base + 3], B->stream));
+        ++B->profiled_steps;
+    }
     for (auto &s : B->host_step) ++s;
     return PA_OK;
 }
@@ -461,6 +484,7 @@ pa_status engine_observables(pa_batch *B, int r, int step, pa_obs *out) {
 }
 
 void engine_destroy(pa_batch *B) {
+    for (hipEvent_t ev : B->events) (void)hipEventDestroy(ev);
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
 }
@@ -620,6 +644,7 @@ pa_status pa_set_population(pa_ctx *ctx, int32_t step, int32_t R_i, const int8_t
     PA_HIP(B, hipStreamSynchronize(B->stream));
     PA_HIP(B, launch_sweeps(B->lc, 1));  // E, M of the adopted population
     PA_HIP(B, launch_adopt_end(B->lc, 0, step, minus_beta_F));
+    PA_HIP(B, launch_hist_current(B->lc));  // the next step reads the histogram
     PA_HIP(B, hipStreamSynchronize(B->stream));
     B->host_step[0] = step;
     return PA_OK;
@@ -667,9 +692,7 @@ pa_status pa_get_state(pa_ctx *ctx, void *buf, size_t cap, size_t *used) {
     h.max_steps = d.max_steps; h.theta = d.theta; h.step = s.step; h.R_i = s.R_cur;
     h.seed = B->cfg[0].seed;
     std::memcpy(p, &h, sizeof h); p += sizeof h;
-    RunState sc = s;
-    for (int k = 0; k < 4; ++k) sc.ticket[k] = 0;
-    std::memcpy(p, &sc, sizeof sc); p += sizeof sc;
+    std::memcpy(p, &s, sizeof s); p += sizeof s;
     const size_t pop = (size_t)(s.R_cur + 63) / 64 * group_bytes(d);
     const void *src = d.layout == PA_LAYOUT_MSC64 ? (const void *)d.ms[s.cur] : (const void *)d.s8[s.cur];
     PA_HIP(B, hipMemcpy(p, src, pop, hipMemcpyDeviceToHost)); p += pop;
@@ -703,7 +726,6 @@ pa_status pa_set_state(pa_ctx *ctx, const void *buf, size_t len) {
     std::memcpy(&s, p, sizeof s); p += sizeof s;
     if (s.cur < 0 || s.cur > 1 || s.R_cur != h.R_i || s.step != h.step || s.err != 0)
         return fail(B, PA_ERR_STATE, "snapshot state is inconsistent");
-    for (int k = 0; k < 4; ++k) s.ticket[k] = 0;
     PA_HIP(B, hipStreamSynchronize(B->stream));
     const size_t pop = (size_t)(s.R_cur + 63) / 64 * group_bytes(d);
     void *dst = d.layout == PA_LAYOUT_MSC64 ? (void *)d.ms[s.cur] : (void *)d.s8[s.cur];
@@ -717,6 +739,8 @@ pa_status pa_set_state(pa_ctx *ctx, const void *buf, size_t len) {
     std::memcpy(B->betas[0].data(), p, (size_t)(d.max_steps + 1) * 8);
     p += (size_t)(d.max_steps + 1) * 8;
     PA_HIP(B, hipMemcpy(d.records, p, (size_t)(s.step + 1) * sizeof(pa_obs), hipMemcpyHostToDevice));
+    PA_HIP(B, launch_hist_current(B->lc));  // the next step reads the histogram
+    PA_HIP(B, hipStreamSynchronize(B->stream));
     B->host_step[0] = s.step;
     return PA_OK;
 }
@@ -745,6 +769,46 @@ pa_status pa_adaptive_dbeta(pa_ctx *ctx, double alpha_target, double dbeta_max, 
     pa_status e = read_state(B, 0, &s);
     if (e) return e;
     *dbeta = s.dbeta_out;
+    return PA_OK;
+}
+
+pa_status pa_profile(pa_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    pa_batch *B = &ctx->b;
+    if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
+    PA_HIP(B, hipStreamSynchronize(B->stream));
+    B->profiling = enable != 0;
+    if (B->profiling) {
+        B->profiled_steps = 0;
+        for (int r = 0; r < B->n; ++r) {
+            unsigned long long zero[2] = {0, 0};
+            PA_HIP(B, hipMemcpy(&B->desc[r].st->philox_calls, zero, sizeof zero, hipMemcpyHostToDevice));
+        }
+    }
+    return PA_OK;
+}
+
+pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, double *ms_sweep,
+                          double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words) {
+    if (!ctx) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    pa_batch *B = &ctx->b;
+    RunState s;
+    pa_status e = read_state(B, 0, &s);
+    if (e) return e;
+    double t[3] = {0, 0, 0};
+    for (int k = 0; k < B->profiled_steps; ++k) {
+        for (int ph = 0; ph < 3; ++ph) {
+            float ms = 0;
+            PA_HIP(B, hipEventElapsedTime(&ms, B->events[4 * k + ph], B->events[4 * k + ph + 1]));
+            t[ph] += ms;
+        }
+    }
+    if (n_steps) *n_steps = B->profiled_steps;
+    if (ms_resample) *ms_resample = t[0];
+    if (ms_sweep) *ms_sweep = t[1];
+    if (ms_measure) *ms_measure = t[2];
+    if (philox_calls) *philox_calls = s.philox_calls;
+    if (sweep_words) *sweep_words = s.sweep_words;
     return PA_OK;
 }
 

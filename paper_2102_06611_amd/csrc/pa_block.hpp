@@ -56,22 +56,6 @@ __device__ inline double block_sum_f64(double v, double *sh) {
     return t;
 }
 
-// Last-block election for a multi-block reduction: returns true in every
-// thread of the block that arrives last; the counter is reset for reuse.
-__device__ inline bool last_block(uint32_t *ticket, uint32_t n_blocks) {
-    __shared__ int am_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = atomicAdd(ticket, 1u);
-        am_last = (t == n_blocks - 1);
-        if (am_last) *ticket = 0;
-    }
-    __syncthreads();
-    if (am_last) __threadfence();
-    return am_last;
-}
-
 // alpha(dbeta) = (1/R) sum_l n_l min(1, R w_l / S) over the histogram of the
 // current population (binary64; the schedule generator needs no exact ties).
 __device__ inline double overlap_block(const RunDesc &rd, int kmin, int nlev, int R, double dbeta,

@@ -27,8 +27,7 @@ struct RunState {
     int32_t R_new;     // size of the population being built in buffer cur ^ 1
     int32_t err;       // sticky pa_status
     int32_t err_step;  // step that raised err
-    int32_t kmin, kmax;          // occupied energy levels entering the resampling
-    uint32_t ticket[4];          // last-block counters of the multi-block reductions
+    int32_t kmin, kmax;          // occupied energy levels of the current population
     double acc_hi, acc_lo;       // running -beta F (double-double)
     double lnq_hi, lnq_lo;       // ln Q of the step in progress (committed by k_reduce)
     uint64_t t4, t8;             // Metropolis thresholds at beta_i (2^32 = always)
@@ -39,6 +38,8 @@ struct RunState {
     int32_t accepted;            // learned proposal passed the overlap guard
     float mlp_y;                 // last MLP output of the learned step
     float pad;
+    unsigned long long philox_calls;  // Philox calls made by the sweeps (profiling)
+    unsigned long long sweep_words;   // 64-replica words updated by the sweeps
 };
 
 // Static description of one run plus pointers into its slice of the workspace.

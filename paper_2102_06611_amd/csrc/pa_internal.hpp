@@ -38,6 +38,7 @@ hipError_t launch_init(const LaunchCtx &c);
 hipError_t launch_sweeps(const LaunchCtx &c, int init);
 hipError_t launch_reduce(const LaunchCtx &c);
 hipError_t launch_step(const LaunchCtx &c);
+hipError_t launch_resample(const LaunchCtx &c);
 hipError_t launch_hist_current(const LaunchCtx &c);
 hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta, double target, int mode);
 hipError_t launch_set_beta(const LaunchCtx &c, int r, int idx, double beta);

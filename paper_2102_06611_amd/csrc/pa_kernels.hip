@@ -3,15 +3,15 @@
 //
 // Step i (Sec. "Algorithm", steps 2-4), with the population entering the step
 // in buffer `cur` and the new one built in buffer `cur ^ 1`:
-//   k_begin        thresholds for beta_i, clear the energy histogram
-//   k_hist         histogram of E over the R_{i-1} parents
-//   k_norm         Q_i of Eq. (Q) over the histogram levels; per-level decision
-//                  integers for the copy counts (Eq. taus / resampling-factors)
-//   k_counts_*     copy counts r_j, block partial sums, R_i (last block)
-//   k_offsets      exclusive prefix sum of r_j (tree order of the children)
+//   k_norm         Metropolis thresholds for beta_i; Q_i of Eq. (Q) over the
+//                  energy histogram; per-level decision integers for the copy
+//                  counts (Eq. taus / resampling-factors)
+//   k_counts_* / k_multi_*   copy counts r_j and per-block partial sums
+//   k_offsets      exclusive prefix sum of r_j (tree order of the children), R_i
 //   k_gather       children <- parents: spins and family labels
 //   k_sweep        theta checkerboard Metropolis sweeps in LDS + E, M
-//   k_reduce       population sums, family statistics, record i (last block)
+//   k_reduce       population sums, family statistics, next energy histogram
+//   k_record       record i; the new population becomes current
 #include <climits>
 
 #include "pa_block.hpp"
@@ -77,48 +77,62 @@ __global__ void k_init_population(const RunDesc *runs, WorkMap map) {
     }
 }
 
-// ------------------------------------------------------------------ step begin
+// ------------------------------------------------------------------ histogram
 
-__global__ void k_begin(const RunDesc *runs) {
-    const RunDesc &rd = runs[blockIdx.x];
-    RunState *st = rd.st;
-    __shared__ int ok;
+// Histogram of the energies of slots [j0, j1): level k = (E + 2N) / 4 <-> E.
+// The block first finds its own level range; when it spans at most kLdsBins
+// levels the counts are gathered in LDS and only occupied levels touch global
+// memory, otherwise each slot adds to the global histogram directly.
+constexpr int kLdsBins = 4096;
+
+__device__ void block_histogram(const RunDesc &rd, RunState *st, int j0, int j1) {
+    __shared__ int32_t bins[kLdsBins];
+    __shared__ int32_t rng[2];
+    const int N = rd.N;
+    int kmin = INT_MAX, kmax = -1;
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
+        const int k = (rd.E[j] + 2 * N) >> 2;
+        kmin = min(kmin, k);
+        kmax = max(kmax, k);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        kmin = min(kmin, __shfl_xor(kmin, o, 64));
+        kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    }
     if (threadIdx.x == 0) {
-        ok = st->err == 0;
-        const int i = st->step + 1;
-        if (ok && i > rd.max_steps) {
-            st->err = PA_ERR_DONE;
-            st->err_step = i;
-            ok = 0;
-        }
-        if (ok) {
-            double b0 = rd.betas[i - 1], b1 = rd.betas[i];
-            if (!(b1 >= b0) || !(b1 <= 1e300)) {
-                st->err = PA_ERR_ARG;
-                st->err_step = i;
-                ok = 0;
-            } else {
-                bool amb = false;
-                st->t4 = metropolis_threshold(b1, 4, &amb);
-                st->t8 = metropolis_threshold(b1, 8, &amb);
-                if (amb) {
-                    st->err = PA_ERR_NUMERIC;
-                    st->err_step = i;
-                    ok = 0;
-                }
-            }
-        }
-        st->kmin = INT_MAX;
-        st->kmax = -1;
-        st->sum_cnt2 = 0;
-        st->w_total = 0;
+        rng[0] = INT_MAX;
+        rng[1] = -1;
     }
     __syncthreads();
-    if (!ok) return;
-    for (int k = threadIdx.x; k < rd.K; k += blockDim.x) rd.hist[k] = 0;
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&rng[0], kmin);
+        atomicMax(&rng[1], kmax);
+    }
+    __syncthreads();
+    const int lo = rng[0], hi = rng[1];
+    if (hi < lo) return;  // empty range (no slots in this block)
+    if (threadIdx.x == 0) {
+        atomicMin(&st->kmin, lo);
+        atomicMax(&st->kmax, hi);
+    }
+    const int span = hi - lo + 1;
+    if (span > kLdsBins) {
+        for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x)
+            atomicAdd(&rd.hist[(rd.E[j] + 2 * N) >> 2], 1);
+        return;
+    }
+    for (int k = threadIdx.x; k < span; k += blockDim.x) bins[k] = 0;
+    __syncthreads();
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x)
+        atomicAdd(&bins[((rd.E[j] + 2 * N) >> 2) - lo], 1);
+    __syncthreads();
+    for (int k = threadIdx.x; k < span; k += blockDim.x)
+        if (bins[k]) atomicAdd(&rd.hist[lo + k], bins[k]);
 }
 
-// Clear the histogram outside a step (overlap / features of the current population).
+// Clear the histogram and rebuild it from the current population (after a
+// population was adopted from the host, and for the overlap / feature queries).
 __global__ void k_hist_clear(const RunDesc *runs) {
     const RunDesc &rd = runs[blockIdx.x];
     if (threadIdx.x == 0) {
@@ -128,37 +142,21 @@ __global__ void k_hist_clear(const RunDesc *runs) {
     for (int k = threadIdx.x; k < rd.K; k += blockDim.x) rd.hist[k] = 0;
 }
 
-// n_k = #{j < R_{i-1} : E_j = -2N + 4k}; k_min, k_max of the occupied levels.
-__global__ void k_hist(const RunDesc *runs, WorkMap map) {
+__global__ void __launch_bounds__(256) k_hist(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
-    if (st->err) return;
-    const int Rp = st->R_cur;
-    int kmin = INT_MAX, kmax = -1;
-    const int j0 = b * kSlotBlock, j1 = min(j0 + kSlotBlock, Rp);
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
-        int k = (rd.E[j] + 2 * rd.N) >> 2;
-        atomicAdd(&rd.hist[k], 1);
-        kmin = min(kmin, k);
-        kmax = max(kmax, k);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        kmin = min(kmin, __shfl_xor(kmin, o, 64));
-        kmax = max(kmax, __shfl_xor(kmax, o, 64));
-    }
-    if ((threadIdx.x & 63) == 0 && kmax >= 0) {
-        atomicMin(&st->kmin, kmin);
-        atomicMax(&st->kmax, kmax);
-    }
+    const int Rc = st->R_cur;
+    block_histogram(rd, st, b * kSlotBlock, min((b + 1) * kSlotBlock, Rc));
 }
 
 // ------------------------------------------------------------------ normalisation
 
-// One block per run.  With dB = beta_i - beta_{i-1} (exact, double-double)
-// and w_l = exp(-4 dB l) the Boltzmann factor of level kmin + l relative to
-// the lowest occupied energy E_min:
+// One block per run, first kernel of step i.  The population entering the
+// step is the current one; its energy histogram n_l (levels kmin + l) was
+// built by the previous step's reduction.  With dB = beta_i - beta_{i-1}
+// (exact, double-double) and w_l = exp(-4 dB l) the Boltzmann factor of level
+// kmin + l relative to the lowest occupied energy E_min:
 //   S = sum_l n_l w_l,   ln Q_i = -dB E_min + ln(S / R_{i-1})          (Eq. Q)
 //   nearest:     Z_l = ceil(2^32 R w_l / S) = ceil(2^32 tau_hat)      (Eq. taus)
 //   multinomial: q_l = floor(2^40 w_l)
@@ -166,18 +164,55 @@ __global__ void k_hist(const RunDesc *runs, WorkMap map) {
 // computed in double-double and a value within the error margin of an integer
 // boundary aborts the run with PA_ERR_NUMERIC.  dB = 0 or a single occupied
 // level make every w_l = 1 and S = R_{i-1} exactly; those use integer math.
+// Also: the Metropolis thresholds t4 = ceil(2^32 e^{-4 beta_i}), t8 =
+// ceil(2^32 e^{-8 beta_i}) and the end-of-schedule check.
 __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     const RunDesc &rd = runs[blockIdx.x];
     RunState *st = rd.st;
-    if (st->err) return;
     __shared__ double sh_hi[256], sh_lo[256];
-    __shared__ int amb_any;
+    __shared__ int amb_any, ok;
     const int i = st->step + 1;
+    if (threadIdx.x == 0) {
+        ok = st->err == 0;
+        amb_any = 0;
+        if (ok && i > rd.max_steps) {
+            st->err = PA_ERR_DONE;
+            st->err_step = i;
+            ok = 0;
+        }
+        if (ok) {
+            const double b0 = rd.betas[i - 1], b1 = rd.betas[i];
+            if (!(b1 >= b0) || !(b1 <= 1e300)) {
+                st->err = PA_ERR_ARG;
+                st->err_step = i;
+                ok = 0;
+            } else if (b1 == 0.0) {
+                st->t4 = st->t8 = 1ull << 32;
+            } else {
+                dd p4;
+                bool amb = false;
+                if (!dd_exp_neg(dd{4.0 * b1, 0.0}, &p4)) {
+                    st->t4 = st->t8 = 1;  // 0 < p < 2^-1000
+                } else {
+                    const dd p8 = dd_mul(p4, p4);  // e^{-8 beta} = (e^{-4 beta})^2
+                    st->t4 = dd_ceil_decided(dd_ldexp(p4, 32), &amb);
+                    st->t8 = p8.hi < 0x1p-990 ? 1 : dd_ceil_decided(dd_ldexp(p8, 32), &amb);
+                }
+                if (amb) {
+                    st->err = PA_ERR_NUMERIC;
+                    st->err_step = i;
+                    ok = 0;
+                }
+            }
+        }
+        st->sum_cnt2 = 0;
+    }
+    __syncthreads();
+    if (!ok) return;
     const int Rp = st->R_cur, kmin = st->kmin, kmax = st->kmax;
     const int nlev = kmax - kmin + 1;
     const dd db = two_sum(rd.betas[i], -rd.betas[i - 1]);
     const bool exact = (db.hi == 0.0) || (nlev == 1);
-    if (threadIdx.x == 0) amb_any = 0;
     dd part{0.0, 0.0};
     for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
         dd w{1.0, 0.0};
@@ -248,35 +283,15 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
 }
 
 // ------------------------------------------------------------------ copy counts
+// Per-slot kernels write one partial sum per block of kSlotBlock slots into
+// part[b * 8 + k]; the next kernel derives block bases and totals by summing
+// those partials itself (no cross-block fences).
 
-// Block partials of the copy counts, then in the last block: exclusive scan of
-// the partials (bases for k_offsets), R_i and sum r_j^2.  part[b*8 + 0..2] =
-// {sum r, sum r^2, base}.
-__device__ void count_partials_tail(const RunDesc &rd, RunState *st, int b, int64_t s,
-                                    int64_t s2) {
-    __shared__ int64_t sh[32];
-    int64_t bs = block_sum_i64(s, sh);
-    int64_t bs2 = block_sum_i64(s2, sh);
-    if (threadIdx.x == 0) {
-        rd.part[b * 8 + 0] = bs;
-        rd.part[b * 8 + 1] = bs2;
-    }
-    if (!last_block(&st->ticket[0], (uint32_t)rd.nblk)) return;
-    if (threadIdx.x == 0) {
-        int64_t run = 0, sq = 0;
-        for (int k = 0; k < rd.nblk; ++k) {
-            rd.part[k * 8 + 2] = run;
-            run += rd.part[k * 8 + 0];
-            sq += rd.part[k * 8 + 1];
-        }
-        if (run > rd.C) {
-            st->err = PA_ERR_CAPACITY;
-            st->err_step = st->step + 1;
-        } else {
-            st->R_new = (int32_t)run;
-            st->sum_cnt2 = sq;
-        }
-    }
+// Sum of part[k * 8 + field] over k in [0, n) by the whole block (fixed order).
+__device__ int64_t block_sum_partials(const RunDesc &rd, int field, int n, int64_t *sh) {
+    int64_t s = 0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) s += rd.part[k * 8 + field];
+    return block_sum_i64(s, sh);
 }
 
 // Nearest-integer rule (Eq. resampling-factors, strict "<"): with
@@ -288,6 +303,7 @@ __global__ void __launch_bounds__(256) k_counts_nearest(const RunDesc *runs, Wor
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
     if (st->err || rd.resample == PA_RESAMPLE_MULTINOMIAL) return;
+    __shared__ int64_t sh[32];
     const int Rp = st->R_cur, i = st->step + 1, kmin = st->kmin;
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
     int64_t s = 0, s2 = 0;
@@ -299,23 +315,29 @@ __global__ void __launch_bounds__(256) k_counts_nearest(const RunDesc *runs, Wor
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            int jj = j + m;
-            if (jj >= Rp) break;
-            int c = 1;
-            if (rd.resample == PA_RESAMPLE_NEAREST) {
-                uint64_t z = rd.zlev[((rd.E[jj] + 2 * rd.N) >> 2) - kmin];
-                c = (int)((z + 0xFFFFFFFFull - u[m]) >> 32);
+            const int jj = j + m;
+            if (jj < Rp) {
+                int c = 1;
+                if (rd.resample == PA_RESAMPLE_NEAREST) {
+                    const uint64_t z = rd.zlev[((rd.E[jj] + 2 * rd.N) >> 2) - kmin];
+                    c = (int)((z + 0xFFFFFFFFull - u[m]) >> 32);
+                }
+                rd.cnt[jj] = c;
+                s += c;
+                s2 += (int64_t)c * c;
             }
-            rd.cnt[jj] = c;
-            s += c;
-            s2 += (int64_t)c * c;
         }
     }
-    count_partials_tail(rd, st, b, s, s2);
+    const int64_t bs = block_sum_i64(s, sh);
+    const int64_t bs2 = block_sum_i64(s2, sh);
+    if (threadIdx.x == 0) {
+        rd.part[b * 8 + 0] = bs;
+        rd.part[b * 8 + 1] = bs2;
+    }
 }
 
 // Multinomial, pass 1: quantised weight q_j of each parent (into cum[j]),
-// zeroed counts, block sums of q; the last block scans them into bases and W.
+// zeroed counts, block sums of q (part[b*8 + 3]).
 __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
@@ -326,26 +348,17 @@ __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, Work
     int64_t s = 0;
     for (int j = b * kSlotBlock + (int)threadIdx.x; j < min((b + 1) * kSlotBlock, Rp);
          j += blockDim.x) {
-        uint64_t q = rd.zlev[((rd.E[j] + 2 * rd.N) >> 2) - kmin];
+        const uint64_t q = rd.zlev[((rd.E[j] + 2 * rd.N) >> 2) - kmin];
         rd.cum[j] = q;
         rd.cnt[j] = 0;
         s += (int64_t)q;
     }
-    int64_t bs = block_sum_i64(s, sh);
+    const int64_t bs = block_sum_i64(s, sh);
     if (threadIdx.x == 0) rd.part[b * 8 + 3] = bs;
-    if (!last_block(&st->ticket[2], (uint32_t)rd.nblk)) return;
-    if (threadIdx.x == 0) {
-        uint64_t run = 0;
-        for (int k = 0; k < rd.nblk; ++k) {
-            uint64_t t = (uint64_t)rd.part[k * 8 + 3];
-            rd.part[k * 8 + 4] = (int64_t)run;
-            run += t;
-        }
-        st->w_total = run;
-    }
 }
 
-// Multinomial, pass 2: inclusive prefix of q_j -> cum[j].
+// Multinomial, pass 2: inclusive prefix of q_j -> cum[j]; block 0 records the
+// total quantised weight W.
 __global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
@@ -353,13 +366,20 @@ __global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap 
     if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
     __shared__ int64_t sh[32];
     const int Rp = st->R_cur;
+    const uint64_t base = (uint64_t)block_sum_partials(rd, 3, b, sh);
+    if (b == 0) {
+        const uint64_t W = (uint64_t)block_sum_partials(rd, 3, rd.nblk, sh);
+        if (threadIdx.x == 0) st->w_total = W;
+    }
+    __shared__ uint64_t base_sh;
+    if (threadIdx.x == 0) base_sh = base;
+    __syncthreads();
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
     uint64_t q[4] = {0, 0, 0, 0};
     for (int m = 0; m < 4; ++m)
         if (j + m < Rp) q[m] = rd.cum[j + m];
     int64_t tot;
-    uint64_t pre = (uint64_t)block_exclusive_scan((int64_t)(q[0] + q[1] + q[2] + q[3]), sh, &tot);
-    uint64_t run = (uint64_t)rd.part[b * 8 + 4] + pre;
+    uint64_t run = base_sh + (uint64_t)block_exclusive_scan((int64_t)(q[0] + q[1] + q[2] + q[3]), sh, &tot);
     for (int m = 0; m < 4; ++m) {
         run += q[m];
         if (j + m < Rp) rd.cum[j + m] = run;
@@ -377,16 +397,16 @@ __global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap
     const uint64_t W = st->w_total;
     const int d0 = b * kSlotBlock + 4 * (int)threadIdx.x;
     for (int h = 0; h < 2; ++h) {
-        int d = d0 + 2 * h;
+        const int d = d0 + 2 * h;
         if (d >= rd.R) break;
         U4 x = philox(rd.key0, rd.key1, (uint32_t)(d >> 1), (uint32_t)i, 0u, kTagMulti);
-        uint64_t U[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
+        const uint64_t U[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
         for (int m = 0; m < 2; ++m) {
             if (d + m >= rd.R) break;
-            uint64_t target = mulhi64(U[m], W);
+            const uint64_t target = mulhi64(U[m], W);
             int lo = 0, hi = Rp - 1;  // first j with cum[j] > target
             while (lo < hi) {
-                int mid = (lo + hi) >> 1;
+                const int mid = (lo + hi) >> 1;
                 if (rd.cum[mid] > target) hi = mid; else lo = mid + 1;
             }
             atomicAdd(&rd.cnt[lo], 1);
@@ -394,51 +414,85 @@ __global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap
     }
 }
 
-// Multinomial, pass 4: block partials of the counts (same tail as nearest).
+// Multinomial, pass 4: block partials of the counts (as k_counts_nearest).
 __global__ void __launch_bounds__(256) k_count_partials(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
     if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    __shared__ int64_t sh[32];
     const int Rp = st->R_cur;
     int64_t s = 0, s2 = 0;
     for (int j = b * kSlotBlock + (int)threadIdx.x; j < min((b + 1) * kSlotBlock, Rp);
          j += blockDim.x) {
-        int64_t c = rd.cnt[j];
+        const int64_t c = rd.cnt[j];
         s += c;
         s2 += c * c;
     }
-    count_partials_tail(rd, st, b, s, s2);
+    const int64_t bs = block_sum_i64(s, sh);
+    const int64_t bs2 = block_sum_i64(s2, sh);
+    if (threadIdx.x == 0) {
+        rd.part[b * 8 + 0] = bs;
+        rd.part[b * 8 + 1] = bs2;
+    }
 }
 
 // off[j] = sum_{l<j} r_l (children of parent j occupy [off[j], off[j] + r_j)),
-// off[R_{i-1}] = R_i.
+// off[R_{i-1}] = R_i.  Block 0 records R_i (or PA_ERR_CAPACITY) and
+// sum r_j^2.  The histogram, consumed by k_norm, is cleared here so that the
+// reduction at the end of the step can build the next one.
 __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
     if (st->err) return;
     __shared__ int64_t sh[32];
+    __shared__ int64_t base_sh;
     const int Rp = st->R_cur;
+    const int64_t base = block_sum_partials(rd, 0, b, sh);
+    if (threadIdx.x == 0) base_sh = base;
+    if (b == 0) {
+        const int64_t total = block_sum_partials(rd, 0, rd.nblk, sh);
+        const int64_t sq = block_sum_partials(rd, 1, rd.nblk, sh);
+        if (threadIdx.x == 0) {
+            if (total > rd.C) {
+                st->err = PA_ERR_CAPACITY;
+                st->err_step = st->step + 1;
+            } else {
+                st->R_new = (int32_t)total;
+                st->sum_cnt2 = sq;
+                rd.off[Rp] = (int32_t)total;
+            }
+            st->kmin = INT_MAX;
+            st->kmax = -1;
+        }
+    }
+    for (int k = b * (int)blockDim.x + (int)threadIdx.x; k < rd.K; k += rd.nblk * (int)blockDim.x)
+        rd.hist[k] = 0;
+    __syncthreads();
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
     int c[4] = {0, 0, 0, 0};
     for (int m = 0; m < 4; ++m)
         if (j + m < Rp) c[m] = rd.cnt[j + m];
     int64_t tot;
-    int64_t pre = block_exclusive_scan(c[0] + c[1] + c[2] + c[3], sh, &tot);
-    int64_t run = rd.part[b * 8 + 2] + pre;
+    int64_t run = base_sh + block_exclusive_scan(c[0] + c[1] + c[2] + c[3], sh, &tot);
     for (int m = 0; m < 4; ++m) {
         if (j + m < Rp) rd.off[j + m] = (int32_t)run;
         run += c[m];
     }
-    if (b == 0 && threadIdx.x == 0) rd.off[Rp] = st->R_new;
 }
 
 // ------------------------------------------------------------------ copy / compaction
 
-// Children c of destination group gd take the spins and family label of
-// parent p(c) = the last j with off[j] <= c; parents stay in ascending order,
-// so the copies of one parent are adjacent (tree order).
+// Child c of destination group gd takes the spins and family label of parent
+// p(c) = the last j with off[j] <= c; parents stay in ascending order, so the
+// copies of one parent are adjacent (tree order).  Every wavefront finds the
+// parents of the group's 64 children (lane = child) and then:
+//  - multispin: lane = site; the destination word is assembled bit by bit from
+//    the parents' words, the parent index broadcast with readlane (uniform),
+//    so each bit costs one extract and one shift-or;
+//  - int8: lane = child; one byte per lane per site row, contiguous in both
+//    the parents' and the children's rows.
 __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map) {
     int gd;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &gd)];
@@ -447,48 +501,65 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
     const int Rn = st->R_new, Rp = st->R_cur;
     if (gd * kLanes >= Rn) return;
     const int cur = st->cur, nb = cur ^ 1, N = rd.N;
-    __shared__ int par[kLanes];
-    if (threadIdx.x < kLanes) {
-        int c = gd * kLanes + threadIdx.x;
-        int p = -1;
-        if (c < Rn) {
-            int lo = 0, hi = Rp;  // off[0..Rp] is non-decreasing, off[0] = 0 <= c < off[Rp]
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (rd.off[mid] <= c) lo = mid; else hi = mid - 1;
-            }
-            p = lo;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int c = gd * kLanes + lane;
+    int p = -1;
+    if (c < Rn) {
+        int lo = 0, hi = Rp;  // off[0..Rp] is non-decreasing, off[0] = 0 <= c < off[Rp]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rd.off[mid] <= c) lo = mid; else hi = mid - 1;
         }
-        par[threadIdx.x] = p;
-        if (c < rd.C) rd.fam[nb][c] = p >= 0 ? rd.fam[cur][p] : 0;
+        p = lo;
     }
-    __syncthreads();
+    if (wave == 0 && c < rd.C) rd.fam[nb][c] = p >= 0 ? rd.fam[cur][p] : 0;
+    const int n_valid = min(kLanes, Rn - gd * kLanes);
     if (rd.layout == PA_LAYOUT_MSC64) {
+        // lane = 4 consecutive sites; the 64 children are unrolled so that the
+        // parent index (readlane) and the bit positions are scalar operands
         const uint64_t *src = rd.ms[cur];
         uint64_t *dst = rd.ms[nb] + (size_t)gd * N;
-        for (int site = threadIdx.x; site < N; site += blockDim.x) {
-            uint64_t w = 0;
-            for (int l = 0; l < kLanes; ++l) {
-                int p = par[l];
-                if (p < 0) break;
-                uint64_t v = src[(size_t)(p >> 6) * N + site];
-                w |= ((v >> (p & 63)) & 1ull) << l;
+        const int nv = __builtin_amdgcn_readfirstlane(n_valid);
+        // parent groups of the children, first and last (the map is monotone)
+        const int g_first = __builtin_amdgcn_readlane(p, 0) >> 6;
+        const int g_last = __builtin_amdgcn_readlane(p, nv - 1) >> 6;
+        for (int site0 = wave * 256; site0 < N; site0 += nw * 256) {
+            const int sb = site0 + 4 * lane;
+            const bool in = sb < N;  // N = L^2 is a multiple of 4
+            uint32_t lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+            for (int pg = g_first; pg <= g_last; ++pg) {
+                uint64_t w[4] = {0, 0, 0, 0};
+                if (in) {
+                    const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(src + (size_t)pg * N + sb);
+                    const ulonglong2 v0 = q[0], v1 = q[1];
+                    w[0] = v0.x; w[1] = v0.y; w[2] = v1.x; w[3] = v1.y;
+                }
+#pragma unroll
+                for (int l = 0; l < kLanes; ++l) {
+                    const int pl = __builtin_amdgcn_readlane(p, l);
+                    if (l < nv && (pl >> 6) == pg) {
+                        const uint32_t sh = (uint32_t)pl & 63u;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t bit = (uint32_t)(w[k] >> sh) & 1u;
+                            if (l < 32) lo[k] |= bit << l; else hi[k] |= bit << (l - 32);
+                        }
+                    }
+                }
             }
-            dst[site] = w;
+            if (in) {
+                uint4 *q = reinterpret_cast<uint4 *>(dst + sb);
+                q[0] = uint4{lo[0], hi[0], lo[1], hi[1]};
+                q[1] = uint4{lo[2], hi[2], lo[3], hi[3]};
+            }
         }
     } else {
         const int8_t *src = rd.s8[cur];
-        uint32_t *dst = reinterpret_cast<uint32_t *>(rd.s8[nb] + (size_t)gd * N * kLanes);
-        for (int it = threadIdx.x; it < N * 16; it += blockDim.x) {
-            int site = it >> 4, q = it & 15;
-            uint32_t word = 0;
-            for (int m = 0; m < 4; ++m) {
-                int p = par[4 * q + m];
-                uint32_t byte = 0xFFu;
-                if (p >= 0) byte = (uint8_t)src[((size_t)(p >> 6) * N + site) * kLanes + (p & 63)];
-                word |= byte << (8 * m);
-            }
-            dst[it] = word;
+        int8_t *dst = rd.s8[nb] + (size_t)gd * N * kLanes;
+        const size_t poff = p >= 0 ? (size_t)(p >> 6) * N * kLanes + (p & 63) : 0;
+        for (int site = wave; site < N; site += nw) {
+            const int8_t v = p >= 0 ? src[poff + (size_t)site * kLanes] : (int8_t)-1;
+            dst[(size_t)site * kLanes + lane] = v;
         }
     }
 }
@@ -505,7 +576,7 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
                                                     uint64_t a4, uint64_t valid, uint64_t t4,
                                                     uint64_t t8, bool all4, bool all8,
                                                     uint32_t k0, uint32_t k1, uint32_t w,
-                                                    uint32_t g, uint32_t h) {
+                                                    uint32_t g, uint32_t h, uint32_t *calls) {
     const uint64_t x12 = a1 ^ a2, y12 = a1 & a2, x34 = a3 ^ a4, y34 = a3 & a4;
     const uint64_t ge2 = y12 | y34 | (x12 & x34);
     const uint64_t any = x12 | y12 | x34 | y34;
@@ -518,19 +589,28 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     eq1 &= valid;
     eq0 &= valid;
     uint64_t und = eq1 | eq0;
-    const uint32_t T4 = (uint32_t)t4, T8 = (uint32_t)t8;
-    for (uint32_t p = 0; und != 0 && p < 16; ++p) {
+    // the thresholds are the same for every lane: keep their bits in scalar registers
+    const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
+    const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
+    uint32_t p = 0;
+    for (; und != 0 && p < 16; ++p) {
         U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
         const uint64_t pa = ((uint64_t)x.y << 32) | x.x;
         const uint64_t pb = ((uint64_t)x.w << 32) | x.z;
         const uint32_t sa = 31u - 2u * p, sb = 30u - 2u * p;
-        uint64_t t = (((T4 >> sa) & 1u) ? eq1 : 0ull) | (((T8 >> sa) & 1u) ? eq0 : 0ull);
-        flip |= und & ~pa & t;
-        und &= ~(pa ^ t);
-        t = (((T4 >> sb) & 1u) ? eq1 : 0ull) | (((T8 >> sb) & 1u) ? eq0 : 0ull);
-        flip |= und & ~pb & t;
-        und &= ~(pb ^ t);
+        // t = threshold bit of each lane: T4's bit for dE = 4 lanes, T8's for dE = 8
+        const uint64_t m4a = 0ull - (uint64_t)((T4 >> sa) & 1u), m8a = 0ull - (uint64_t)((T8 >> sa) & 1u);
+        const uint64_t m4b = 0ull - (uint64_t)((T4 >> sb) & 1u), m8b = 0ull - (uint64_t)((T8 >> sb) & 1u);
+        uint64_t t = (eq1 & m4a) | (eq0 & m8a);
+        uint64_t d = pa ^ t;          // lanes decided by this plane
+        flip |= und & d & t;          // ... in favour of u < T
+        und &= ~d;
+        t = (eq1 & m4b) | (eq0 & m8b);
+        d = pb ^ t;
+        flip |= und & d & t;
+        und &= ~d;
     }
+    *calls += p;
     return flip;
 }
 
@@ -573,6 +653,7 @@ __global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map,
     const uint64_t t4 = st->t4, t8 = st->t8;
     const bool all4 = t4 >= (1ull << 32), all8 = t8 >= (1ull << 32);
     const float inv_half = 1.0f / (float)half;
+    uint32_t calls = 0;
     for (int s = 0; s < theta; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
@@ -591,7 +672,7 @@ __global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map,
                 const uint64_t f = metropolis_word(s0 ^ lat[row + xr], s0 ^ lat[row + xl],
                                                    s0 ^ lat[up + x], s0 ^ lat[dn + x], valid, t4,
                                                    t8, all4, all8, rd.key0, rd.key1,
-                                                   (uint32_t)wi, (uint32_t)g, h);
+                                                   (uint32_t)wi, (uint32_t)g, h, &calls);
                 lat[row + x] = s0 ^ f;
             }
             __syncthreads();
@@ -615,6 +696,12 @@ __global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map,
         atomicAdd(&red_u[lane], U);
         atomicAdd(&red_up[lane], upc);
     }
+    {  // Philox calls of this block (one atomic per wave)
+        uint64_t c64 = wave_sum_i64((int64_t)calls);
+        if ((tid & 63) == 0 && theta > 0) atomicAdd(&st->philox_calls, (unsigned long long)c64);
+        if (tid == 0 && theta > 0)
+            atomicAdd(&st->sweep_words, (unsigned long long)theta * (unsigned long long)N);
+    }
     __syncthreads();
     if (tid < kLanes) {
         const int c = g * kLanes + tid;
@@ -637,11 +724,13 @@ __global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map,
 
 // ------------------------------------------------------------------ reduction + record
 
-// Population sums over R_i replicas and family statistics from the tree-ordered
-// labels (families are contiguous runs: a run ending at slot c has length
-// c - first(c) + 1, first(c) found by binary search); the last block writes
-// record i (Sec. "Model and observables" with N -> R_i; Eqs. rhot, rhos,
-// one-step-Reff) and makes the new population current.
+// Population sums over the R_i replicas and family statistics from the
+// tree-ordered labels: families are contiguous runs, a run ending at slot c
+// has length c - first(c) + 1.  first(c) comes from a block max-scan of the
+// run starts; a run entering the block from the left is located once per
+// block by binary search.  The block also adds its slots to the energy
+// histogram that the next step's k_norm reads.  Partials go to part[b*8 + k],
+// partd[b*2]; k_record combines them.
 __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
@@ -649,45 +738,97 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     if (st->err) return;
     __shared__ int64_t sh[32];
     __shared__ double shd[32];
+    __shared__ int first_start;
     const int Rn = st->R_new, nb = st->cur ^ 1;
     const int32_t *fam = rd.fam[nb];
-    int64_t sE = 0, sE2 = 0, sM = 0, sM2 = 0, f = 0, s2 = 0;
-    double cl = 0.0;
-    for (int c = b * kSlotBlock + (int)threadIdx.x; c < min((b + 1) * kSlotBlock, Rn);
-         c += blockDim.x) {
-        int64_t e = rd.E[c], m = rd.M[c];
-        sE += e;
-        sE2 += e * e;
-        sM += m < 0 ? -m : m;
-        sM2 += m * m;
-        int fc = fam[c];
-        if (c == Rn - 1 || fam[c + 1] != fc) {
-            int lo = 0, hi = c;  // first slot with fam == fc
+    const int j0 = b * kSlotBlock, j1 = min(j0 + kSlotBlock, Rn);
+    if (threadIdx.x == 0) {
+        int s0 = 0;
+        if (j0 < Rn && j0 > 0 && fam[j0 - 1] == fam[j0]) {
+            int lo = 0, hi = j0;  // first slot with fam == fam[j0]
+            const int fc = fam[j0];
             while (lo < hi) {
-                int mid = (lo + hi) >> 1;
+                const int mid = (lo + hi) >> 1;
                 if (fam[mid] < fc) lo = mid + 1; else hi = mid;
             }
-            int64_t len = c - lo + 1;
+            s0 = lo;
+        } else {
+            s0 = j0;
+        }
+        first_start = s0;
+    }
+    __syncthreads();
+    // each thread owns 4 consecutive slots
+    const int c0 = j0 + 4 * (int)threadIdx.x;
+    int last_start = -1;  // start of the run containing the thread's last slot, within the thread
+    int starts[4];
+    for (int m = 0; m < 4; ++m) {
+        const int c = c0 + m;
+        starts[m] = -1;
+        if (c < j1 && (c == j0 || fam[c - 1] != fam[c])) starts[m] = (c == j0) ? first_start : c;
+        if (starts[m] >= 0) last_start = starts[m];
+    }
+    // exclusive max-scan of last_start over threads gives the run start entering each thread
+    int x = last_start;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x = max(x, y);
+    }
+    __shared__ int wmax[16];
+    if (lane == 63) wmax[wave] = x;
+    __syncthreads();
+    int prev = -1;
+    for (int w = 0; w < wave; ++w) prev = max(prev, wmax[w]);
+    const int up = __shfl_up(x, 1, 64);
+    if (lane > 0) prev = max(prev, up);
+    int64_t sE = 0, sE2 = 0, sM = 0, sM2 = 0, f = 0, s2 = 0;
+    double cl = 0.0;
+    int run_start = prev;
+    for (int m = 0; m < 4; ++m) {
+        const int c = c0 + m;
+        if (c >= j1) break;
+        if (starts[m] >= 0) run_start = starts[m];
+        const int64_t e = rd.E[c], mm = rd.M[c];
+        sE += e;
+        sE2 += e * e;
+        sM += mm < 0 ? -mm : mm;
+        sM2 += mm * mm;
+        if (c == Rn - 1 || fam[c + 1] != fam[c]) {
+            const int64_t len = c - run_start + 1;
             f += 1;
             s2 += len * len;
             cl += (double)len * log((double)len);
         }
     }
-    int64_t v[6] = {sE, sE2, sM, sM2, f, s2};
+    const int64_t v[6] = {sE, sE2, sM, sM2, f, s2};
     for (int k = 0; k < 6; ++k) {
-        int64_t t = block_sum_i64(v[k], sh);
+        const int64_t t = block_sum_i64(v[k], sh);
         if (threadIdx.x == 0) rd.part[b * 8 + k] = t;
     }
-    double tcl = block_sum_f64(cl, shd);
+    const double tcl = block_sum_f64(cl, shd);
     if (threadIdx.x == 0) rd.partd[b * 2] = tcl;
-    if (!last_block(&st->ticket[1], (uint32_t)rd.nblk)) return;
+    block_histogram(rd, st, j0, j1);
+}
+
+// One block per run: combine the partials of k_reduce, write record i (Sec.
+// "Model and observables" with N -> R_i; Eqs. rhot, rhos, one-step-Reff) and
+// make the new population current.
+__global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
+    const RunDesc &rd = runs[blockIdx.x];
+    RunState *st = rd.st;
+    if (st->err) return;
+    __shared__ int64_t sh[32];
+    __shared__ double shd[32];
+    const int Rn = st->R_new, nb = st->cur ^ 1;
+    const int nblk = (Rn + kSlotBlock - 1) / kSlotBlock;
+    int64_t T[6];
+    for (int q = 0; q < 6; ++q) T[q] = block_sum_partials(rd, q, nblk, sh);
+    double c = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) c += rd.partd[k * 2];
+    const double TCL = block_sum_f64(c, shd);
     if (threadIdx.x != 0) return;
-    int64_t T[6] = {0, 0, 0, 0, 0, 0};
-    double TCL = 0.0;
-    for (int k = 0; k < rd.nblk; ++k) {
-        for (int q = 0; q < 6; ++q) T[q] += rd.part[k * 8 + q];
-        TCL += rd.partd[k * 2];
-    }
     const int step = st->step + 1;
     const double beta = rd.betas[step];
     if (step > 0) {  // -beta_i F_i = -beta_{i-1} F_{i-1} + ln Q_i, now that step i is complete
@@ -863,12 +1004,11 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init) {
 
 hipError_t launch_reduce(const LaunchCtx &c) {
     PA_LAUNCH(k_reduce, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+    PA_LAUNCH(k_record, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
     return hipSuccess;
 }
 
-hipError_t launch_step(const LaunchCtx &c) {
-    PA_LAUNCH(k_begin, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
-    PA_LAUNCH(k_hist, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+hipError_t launch_resample(const LaunchCtx &c) {
     PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
     if (c.any_nearest)
         PA_LAUNCH(k_counts_nearest, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
@@ -885,7 +1025,13 @@ hipError_t launch_step(const LaunchCtx &c) {
     }
     PA_LAUNCH(k_offsets, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
     PA_LAUNCH(k_gather, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
-    hipError_t e = launch_sweeps(c, 0);
+    return hipSuccess;
+}
+
+hipError_t launch_step(const LaunchCtx &c) {
+    hipError_t e = launch_resample(c);
+    if (e != hipSuccess) return e;
+    e = launch_sweeps(c, 0);
     if (e != hipSuccess) return e;
     return launch_reduce(c);
 }

@@ -1,0 +1,222 @@
+"""GPU tests of the batched engine, the adaptive schedule and the learned
+(perceptron) schedule, against the CPU oracle and against single runs."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_2102_06611_amd as pa
+from paper_2102_06611_amd import schedules
+from oracle import mlp
+from oracle import pa_oracle as po
+from workloads import PARITY_SEED, linear_schedule
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pa.lib()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def test_batch_of_uneven_runs_matches_single_runs_and_oracle():
+    n = 5
+    specs = [dict(L=8, R=100, theta=2, seed=21, resample="nearest", layout="msc64"),
+             dict(L=16, R=300, theta=3, seed=22, resample="multinomial", layout="int8"),
+             dict(L=6, R=70, theta=1, seed=23, resample="nearest", layout="msc64"),
+             dict(L=8, R=64, theta=2, seed=24, resample="nearest", layout="int8"),
+             dict(L=16, R=129, theta=2, seed=25, resample="nearest", layout="msc64")]
+    for k, s in enumerate(specs):
+        s["betas"] = linear_schedule(0.3 + 0.1 * k, n)
+    stream = torch.cuda.Stream()
+    b = pa.Batch(specs, stream=stream)
+    b.run(n)
+    b.sync()
+    for k, s in enumerate(specs):
+        single = pa.Run(s["L"], s["R"], s["betas"], s["theta"], s["seed"], s["resample"],
+                        s["layout"])
+        single.run(n)
+        for i in range(n + 1):
+            assert b.observables(k, i) == single.observables(i), (k, i)
+        single.close()
+    ref = po.run(8, 100, specs[0]["betas"], 2, 21, "nearest")
+    for i in range(n + 1):
+        got = b.observables(0, i)
+        assert got["sum_E"] == ref.records[i].sum_E and got["R_i"] == ref.records[i].R_i
+    b.close()
+
+
+def test_batch_covering_design_runs_and_replays():
+    from workloads import batched_design
+    specs = []
+    for rs in batched_design(8, beta_final=0.4407, n_steps=6, theta=2):
+        specs.append(dict(L=rs.L // 2, R=rs.R // 10, theta=rs.theta, seed=rs.seed,
+                          resample=rs.resample, layout=rs.layout, betas=rs.betas()))
+    stream = torch.cuda.Stream()
+    b = pa.Batch(specs, stream=stream)
+    b.run(3)
+    b.run(3)  # the captured graph is replayed
+    b.sync()
+    for k in (0, 5):
+        s = specs[k]
+        single = pa.Run(s["L"], s["R"], s["betas"], s["theta"], s["seed"], s["resample"],
+                        s["layout"])
+        single.run(6)
+        assert b.observables(k, 6) == single.observables(6)
+        single.close()
+    b.close()
+
+
+def _population_after(L, R, steps, bf=0.44, theta=3, seed=31):
+    betas = linear_schedule(bf, 20)
+    run = pa.Run(L, R, betas, theta, seed, "nearest", "msc64")
+    for _ in range(steps):
+        run.anneal_step()
+    _, _, E, _ = run.population(spins=False)
+    return run, E, betas[steps]
+
+
+@pytest.mark.parametrize("dbeta", [0.0, 0.003, 0.02, 0.1])
+def test_overlap_matches_oracle(dbeta):
+    run, E, _ = _population_after(16, 3000, 8)
+    a = run.overlap(dbeta)
+    assert abs(a - po.overlap(E, dbeta)) < 1e-9
+    if dbeta == 0.0:
+        assert a == 1.0
+    run.close()
+
+
+def test_adaptive_dbeta_hits_the_target_overlap():
+    run, E, _ = _population_after(16, 3000, 10)
+    for target in (0.7, 0.85, 0.95):
+        d = run.adaptive_dbeta(target, 0.5)
+        assert 0 < d < 0.5
+        assert abs(po.overlap(E, d) - target) < 1e-6
+    # a target already met by the largest step returns that step
+    assert run.adaptive_dbeta(1e-6, 0.001) == 0.001
+    run.close()
+
+
+def test_adaptive_schedule_replays_in_the_oracle():
+    L, R, theta = 8, 400, 2
+    run = schedules.adaptive_run(L, R, theta, 41, 0.85, 0.6, max_steps=300)
+    n, acc, alpha = run.schedule_log()
+    assert n > 3 and run.observables(n)["beta"] == 0.6
+    assert np.all(alpha >= 0.85 - 1e-9) and not acc.any()
+    betas = [run.observables(i)["beta"] for i in range(n + 1)]
+    ref = po.OracleRun(L, R, theta, 41, "nearest", np.array(betas))
+    for i in range(1, n + 1):
+        # the step the device chose has the target overlap in the oracle too
+        if i < n:
+            assert abs(po.overlap(ref.E, betas[i] - betas[i - 1]) - 0.85) < 1e-6
+        ref.anneal_step()
+        got = run.observables(i)
+        assert got["sum_E"] == ref.records[i].sum_E and got["R_i"] == ref.records[i].R_i
+        assert abs(got["minus_beta_F"] - ref.records[i].minus_beta_F) < 1e-12 * abs(got["minus_beta_F"])
+    run.close()
+
+
+def _rand_params(seed):
+    rng = np.random.default_rng(seed)
+    p = mlp.init_params(seed) + rng.normal(0, 0.05, mlp.N_PARAMS)
+    return p
+
+
+def test_mlp_forward_matches_fp64_oracle():
+    p = _rand_params(1)
+    X = np.random.default_rng(2).normal(0, 1, (301, mlp.N_IN))
+    dp = torch.tensor(p, dtype=torch.float32, device="cuda")
+    dx = torch.tensor(X, dtype=torch.float32, device="cuda")
+    dy = torch.zeros(301, dtype=torch.float32, device="cuda")
+    pa.mlp_forward(dp, dx, dy)
+    torch.cuda.synchronize()
+    y, _, _ = mlp.forward(p, X)
+    assert np.max(np.abs(dy.cpu().numpy() - y) / (1 + np.abs(y))) < 1e-4
+
+
+def test_mlp_backward_matches_fp64_oracle():
+    p = _rand_params(3)
+    rng = np.random.default_rng(4)
+    X = rng.normal(0, 1, (257, mlp.N_IN))
+    T = rng.normal(0, 1, 257)
+    dp = torch.tensor(p, dtype=torch.float32, device="cuda")
+    dx = torch.tensor(X, dtype=torch.float32, device="cuda")
+    dt = torch.tensor(T, dtype=torch.float32, device="cuda")
+    dg = torch.zeros(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    dl = torch.zeros(1, dtype=torch.float32, device="cuda")
+    pa.mlp_backward(dp, dx, dt, dg, dl)
+    torch.cuda.synchronize()
+    L0, g = mlp.loss_and_grad(p, X, T)
+    gd = dg.cpu().numpy()
+    assert abs(dl.item() - L0) < 1e-4 * (1 + L0)
+    assert np.max(np.abs(gd - g)) < 1e-4 * (np.max(np.abs(g)) + 1e-3)
+
+
+def test_mlp_training_follows_fp64_adam():
+    rng = np.random.default_rng(5)
+    X = rng.normal(0, 1, (200, mlp.N_IN))
+    T = np.sin(X[:, 0]) + 0.5 * X[:, 1]
+    p0 = _rand_params(6)
+    dp = torch.tensor(p0, dtype=torch.float32, device="cuda")
+    adam = torch.zeros(2 * mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    dl = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dx = torch.tensor(X, dtype=torch.float32, device="cuda")
+    dt = torch.tensor(T, dtype=torch.float32, device="cuda")
+    p, m, v = p0.copy(), np.zeros(mlp.N_PARAMS), np.zeros(mlp.N_PARAMS)
+    for t in range(1, 51):
+        pa.mlp_train_step(dp, adam, dx, dt, 1e-3, t, dl)
+        _, g = mlp.loss_and_grad(p, X, T)
+        p, m, v = mlp.adam_step(p, m, v, g, 1e-3, t)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(dp.cpu().numpy() - p)) < 2e-4
+    assert mlp.loss(p, X, T) < mlp.loss(p0, X, T)
+
+
+def test_features_match_oracle():
+    run, E, beta = _population_after(16, 2000, 7)
+    f = torch.zeros(mlp.N_IN, dtype=torch.float32, device="cuda")
+    run.features(f)
+    torch.cuda.synchronize()
+    want = mlp.features(E, beta, 256)
+    assert np.allclose(f.cpu().numpy(), want.astype(np.float32), rtol=1e-6, atol=1e-7)
+    run.close()
+
+
+def test_learned_proposal_is_guarded_by_the_overlap():
+    run, E, beta = _population_after(16, 3000, 9)
+    for seed in range(4):
+        p = _rand_params(10 + seed)
+        p[-1] = -1.0 + 0.6 * seed  # spread the proposals
+        dp = torch.tensor(p, dtype=torch.float32, device="cuda")
+        d, accepted = run.learned_dbeta(dp, 0.8, 0.85, 0.3)
+        if accepted:
+            assert po.overlap(E, d) >= 0.8 - 1e-9
+            y, _, _ = mlp.forward(p, mlp.features(E, beta, 256)[None, :])
+            sd = math.sqrt(mlp.features(E, beta, 256)[34] * 256)
+            assert abs(d - min(math.exp(y[0]) / sd, 0.3)) < 1e-4 * d
+        else:
+            assert d == run.adaptive_dbeta(0.85, 0.3)
+    run.close()
+
+
+def test_learned_schedule_runs_and_logs():
+    L, R = 16, 2000
+    p = _rand_params(20)
+    p[-1] = -1.0
+    dp = torch.tensor(p, dtype=torch.float32, device="cuda")
+    run = schedules.learned_run(dp, L, R, 2, 51, 0.8, 0.85, 0.5, max_steps=500)
+    n, acc, alpha = run.schedule_log()
+    assert run.observables(n)["beta"] == 0.5
+    assert np.all(alpha >= 0.8 - 1e-9)
+    X, t = schedules.training_rows(run)
+    assert X.shape[0] == t.shape[0] <= n and torch.isfinite(t).all()
+    run.close()
