@@ -28,10 +28,11 @@ SEED = 12345
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: full-rate 32-bit VALU lane-operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU issue slots (full-rate lane-ops) of the minimal work, see the design doc:
-SLOTS_PER_PHILOX = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
-SLOTS_PER_PLANE_PAIR = 40  # lazy comparison of two 64-bit planes against the thresholds
-SLOTS_PER_WORD = 24      # neighbour XORs and the bit-sliced A >= 2 / A = 1 / A = 0 classes
+# Algorithmic VALU work (full-rate lane-operations) of the minimal gfx950 instruction
+# sequence for the work actually needed:
+SLOTS_PER_PHILOX = 40      # 10 rounds x (2 v_mad_u64_u32 + 2 three-input XORs)
+SLOTS_PER_PLANE_PAIR = 16  # two 64-bit planes x two halves x (threshold bit, accept, tie, or)
+SLOTS_PER_WORD = 24        # neighbour XORs and the bit-sliced A >= 2 / A = 1 / A = 0 classes
 
 
 def log(msg):
@@ -59,16 +60,19 @@ def measured_traffic(kernel: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def time_layout(pa, torch, betas, layout, K, W):
+def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial", seed=SEED):
+    from paper_2102_06611_amd import autotune
     stream = torch.cuda.Stream()
-    # warmup: W steps of a separate run (compiles nothing; brings clocks and caches up)
+    # warmup: W steps of a separate run (brings clocks and caches up)
     if W > 0:
-        w = pa.Run(L, R, betas, THETA, SEED + 1, "multinomial", layout, stream=stream)
-        for _ in range(min(W, N_STEPS)):
+        w = pa.Run(L, R, betas, THETA, seed + 1, resample, layout, stream=stream)
+        autotune.apply(w, L, R, layout)
+        for _ in range(min(W, len(betas) - 1)):
             w.anneal_step()
         w.sync()
         w.close()
-    run = pa.Run(L, R, betas, THETA, SEED, "multinomial", layout, stream=stream)
+    run = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream)
+    geometry = autotune.apply(run, L, R, layout) or run.sweep_launch(L)
     run.sync()
     run.profile(True)
     torch.cuda.synchronize()
@@ -81,7 +85,36 @@ def time_layout(pa, torch, betas, layout, K, W):
     prof = run.profile_read()
     recs = [run.observables(i) for i in range(K + 1)]
     attempts = sum(r["R_i"] for r in recs[1:]) * L * L * THETA
+    prof["geometry"] = list(geometry)
     return run, wall, prof, recs, attempts
+
+
+def time_batch(pa, torch, K):
+    """64 independent runs, L in {16,32,64,128} x R in {1e3,5e3,2e4,5e4}, graph-replayed."""
+    from paper_2102_06611_amd import autotune
+    from workloads import batched_design
+    design = batched_design(64, beta_final=0.4407, n_steps=200, theta=THETA)
+    specs = [dict(L=d.L, R=d.R, theta=d.theta, seed=d.seed, resample=d.resample, layout=d.layout,
+                  betas=d.betas()) for d in design]
+    stream = torch.cuda.Stream()
+    b = pa.Batch(specs, stream=stream)
+    for Lc in sorted(set(d.L for d in design)):
+        autotune.apply(b, Lc, 20000, "msc64")
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(K)
+    b.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    attempts = 0
+    for k, d in enumerate(design):
+        attempts += sum(b.observables(k, i)["R_i"] for i in range(1, K + 1)) * d.L * d.L * THETA
+    b.close()
+    return {"attempts_per_ns": attempts / wall / 1e9, "ms_per_step": wall * 1e3 / K, "steps": K,
+            "runs": len(design), "spins": sum(d.L * d.L * d.R for d in design),
+            "workload": "64 runs, L in {16,32,64,128} x R in {1000,5000,20000,50000} (each pair 4x), "
+                        "nearest, multispin, beta 0->0.4407 in 200 steps, theta=10, one HIP graph per step"}
 
 
 def cpu_baseline(betas, energies):
@@ -125,6 +158,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layouts", default="msc64,int8")
+    ap.add_argument("--headline-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs one population per device and "
@@ -171,6 +205,7 @@ def main():
             "resample_copy_bytes": copy_bytes,
             "beta_f_error_per_spin": {"at_last_step": err[-1], "max": max(err)},
             "beta_last": recs[-1]["beta"],
+            "sweep_geometry": prof["geometry"],
         }
         if layout == head_candidate(args.layouts) and not args.no_cpu_baseline:
             # energies entering step 101, for the CPU-baseline resampling sample
@@ -180,6 +215,26 @@ def main():
             _, _, energies_mid, _ = e_run.population(spins=False)
             e_run.close()
         run.close()
+        torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.headline_only:
+        log("timing L=128, R=100000, nearest, multispin: 400 steps")
+        betas128 = linear_schedule(1.0, 400)
+        lnz128 = exact["schedules"]["L128_1_400"]["ln_z"]
+        run, wall, prof, recs, attempts = time_layout(pa, torch, betas128, "msc64", 400, 0, L=128,
+                                                      R=100_000, resample="nearest")
+        n = prof["steps"]
+        extra["l128_nearest_msc64"] = {
+            "attempts_per_ns": attempts / wall / 1e9, "ms_per_step": wall * 1e3 / 400,
+            "sweep_attempts_per_ns": attempts / (prof["ms_sweep"] * 1e-3) / 1e9,
+            "resample_us_per_step": prof["ms_resample"] / n * 1e3, "geometry": prof["geometry"],
+            "beta_f_error_per_spin": abs(recs[-1]["minus_beta_F"] - lnz128[-1]) / (128 * 128),
+            "final_families": recs[-1]["n_families"], "final_rho_t": recs[-1]["rho_t"]}
+        run.close()
+        torch.cuda.empty_cache()
+        log("timing the 64-run batch: 200 steps")
+        extra["batched_64_runs"] = time_batch(pa, torch, 200)
         torch.cuda.empty_cache()
 
     head_layout = "msc64" if "msc64" in results else list(results)[0]
@@ -201,6 +256,7 @@ def main():
         "resample_us_per_step": head["resample_us_per_step"],
         "roofline": roof,
         "layouts": results,
+        "workloads": extra,
     }
     if not args.no_cpu_baseline and energies_mid is not None:
         log("timing the CPU oracle sample")

@@ -191,6 +191,19 @@ pa_status pa_profile(pa_ctx *ctx, int32_t enable);
 pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, double *ms_sweep,
                           double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words);
 
+/* Launch geometry of the sweep kernel for the runs of lattice side L: threads
+ * per block (a multiple of 64 in [64, 1024]), 64-replica groups per block
+ * (1..8, with groups_per_block * L^2 * 8 bytes <= 152 KiB of LDS) and the
+ * variant of the plane-by-plane comparison: 0 runs each word's comparison to
+ * the end in its own lane, 1 pools the words still undecided after three
+ * Philox calls in per-wavefront lists.  The results do not depend on any of
+ * it (the random numbers are keyed by replica and site); only speed does.
+ * Synchronises. */
+pa_status pa_set_sweep_launch(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_block,
+                              int32_t variant);
+pa_status pa_get_sweep_launch(pa_ctx *ctx, int32_t L, int32_t *threads, int32_t *groups_per_block,
+                              int32_t *variant);
+
 /* Release host-side state; NULL-safe; does not free the workspace. */
 void pa_destroy(pa_ctx *ctx);
 
@@ -208,6 +221,10 @@ pa_status pa_batch_create(const pa_config *cfgs, int32_t n_runs, void *dev_works
 pa_status pa_batch_run(pa_batch *b, int32_t n_steps);
 pa_status pa_batch_observables(pa_batch *b, int32_t run, int32_t step, pa_obs *out);
 pa_status pa_batch_sync(pa_batch *b);
+pa_status pa_batch_set_sweep_launch(pa_batch *b, int32_t L, int32_t threads,
+                                    int32_t groups_per_block, int32_t variant);
+pa_status pa_batch_get_sweep_launch(pa_batch *b, int32_t L, int32_t *threads,
+                                    int32_t *groups_per_block, int32_t *variant);
 void pa_batch_destroy(pa_batch *b);
 const char *pa_batch_last_error(const pa_batch *b);
 

@@ -104,6 +104,10 @@ SIGNATURES = {
     "pa_anneal_step_learned": (_i32, [_vp, _vp, _dbl, _dbl, _dbl]),
     "pa_schedule_log": (_i32, [_vp, _vp, _vp, _P(_i32), _P(_dbl), _i32, _P(_i32)]),
     "pa_profile": (_i32, [_vp, _i32]),
+    "pa_set_sweep_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
+    "pa_get_sweep_launch": (_i32, [_vp, _i32, _P(_i32), _P(_i32), _P(_i32)]),
+    "pa_batch_set_sweep_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
+    "pa_batch_get_sweep_launch": (_i32, [_vp, _i32, _P(_i32), _P(_i32), _P(_i32)]),
     "pa_profile_read": (_i32, [_vp, _P(_i32), _P(_dbl), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64)]),
 }
 
@@ -267,6 +271,15 @@ class Run:
     def features(self, dev_feat) -> None:
         _check(lib().pa_features(self.h, ctypes.c_void_p(dev_feat.data_ptr())), self.h)
 
+    def set_sweep_launch(self, L: int, threads: int, groups_per_block: int, variant: int = 0):
+        _check(lib().pa_set_sweep_launch(self.h, L, threads, groups_per_block, variant), self.h)
+
+    def sweep_launch(self, L: int):
+        t, g, v = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pa_get_sweep_launch(self.h, L, ctypes.byref(t), ctypes.byref(g),
+                                         ctypes.byref(v)), self.h)
+        return t.value, g.value, v.value
+
     def profile(self, enable: bool = True):
         _check(lib().pa_profile(self.h, 1 if enable else 0), self.h)
 
@@ -337,6 +350,16 @@ class Batch:
 
     def run(self, n_steps: int):
         _check(lib().pa_batch_run(self.h, int(n_steps)), self.h, batch=True)
+
+    def set_sweep_launch(self, L: int, threads: int, groups_per_block: int, variant: int = 0):
+        _check(lib().pa_batch_set_sweep_launch(self.h, L, threads, groups_per_block, variant),
+               self.h, batch=True)
+
+    def sweep_launch(self, L: int):
+        t, g, v = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pa_batch_get_sweep_launch(self.h, L, ctypes.byref(t), ctypes.byref(g),
+                                               ctypes.byref(v)), self.h, batch=True)
+        return t.value, g.value, v.value
 
     def sync(self):
         _check(lib().pa_batch_sync(self.h), self.h, batch=True)

@@ -147,6 +147,7 @@ struct EngineLayout {
         int total;
         int n;
         bool msc, i8;
+        std::vector<int> runs;  // runs with this L
     };
     std::vector<Cls> classes;
 };
@@ -187,6 +188,7 @@ EngineLayout layout_engine(const pa_config *cfgs, int n) {
         c.at = E.maps.add(rs, gs, &c.total);
         c.msc = msc;
         c.i8 = i8;
+        c.runs = rs;
         E.classes.push_back(c);
     }
     E.off_descs = o;
@@ -204,6 +206,18 @@ void dd_n_ln2(int N, double *hi, double *lo) {
     double s = p + e;
     *hi = s;
     *lo = e - (s - p);
+}
+
+// Default sweep geometry: enough 64-replica groups per block for ~512 words
+// per half-sweep (small lattices), and 1024 threads when a block's LDS is so
+// large that only one block fits on a CU.
+void default_sweep_launch(int L, int *threads, int *gpb) {
+    const int N = L * L;
+    int g = 512 / (N / 2);
+    g = std::max(1, std::min(8, g));
+    while (g > 1 && (size_t)g * N * 8 > (size_t)kMaxSweepLds) --g;
+    *gpb = g;
+    *threads = ((size_t)g * N * 8 > 80 * 1024) ? 512 : 256;
 }
 
 std::once_flag g_config_once;
@@ -227,6 +241,7 @@ struct pa_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dead = false;
+    std::vector<std::vector<int32_t>> class_maps;  // host copies of uploaded sweep maps
     // phase timing (pa_profile)
     bool profiling = false;
     std::vector<hipEvent_t> events;  // 4 per profiled step
@@ -264,6 +279,24 @@ pa_status workspace_size(const pa_config *cfgs, int n, size_t *bytes) {
     for (int r = 0; r < n; ++r)
         if (!validate(cfgs[r], &why)) return fail(nullptr, PA_ERR_ARG, why);
     *bytes = layout_engine(cfgs, n).bytes;
+    return PA_OK;
+}
+
+// (Re)write the block offsets of sweep class k for its groups-per-block.
+pa_status upload_class_map(pa_batch *B, int k) {
+    const auto &c = B->lay.classes[k];
+    SweepClass &sc = B->lc.sweep_classes[k];
+    std::vector<int32_t> off(c.runs.size() + 1);
+    int acc = 0;
+    for (size_t q = 0; q < c.runs.size(); ++q) {
+        off[q] = acc;
+        acc += (B->lay.plans[c.runs[q]].G + sc.gpb - 1) / sc.gpb;
+    }
+    off[c.runs.size()] = acc;
+    sc.total = acc;
+    B->class_maps.push_back(off);  // keep the host copy alive for the async copy
+    PA_HIP(B, hipMemcpyAsync((void *)sc.map.blk_off, B->class_maps.back().data(), off.size() * 4,
+                             hipMemcpyHostToDevice, B->stream));
     return PA_OK;
 }
 
@@ -379,9 +412,14 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         sc.total = c.total;
         sc.has_msc = c.msc;
         sc.has_int8 = c.i8;
+        default_sweep_launch(c.L, &sc.threads, &sc.gpb);
+        sc.pooled = 0;
         lc.sweep_classes.push_back(sc);
     }
-    lc.sweep_threads = 256;
+    for (size_t k = 0; k < lc.sweep_classes.size(); ++k) {
+        pa_status e = upload_class_map(B, (int)k);
+        if (e) return e;
+    }
     lc.any_nearest = lc.any_multi = false;
     for (int r = 0; r < n; ++r) {
         if (cfgs[r].resample == PA_RESAMPLE_MULTINOMIAL) lc.any_multi = true;
@@ -391,6 +429,7 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
     PA_HIP(B, launch_sweeps(lc, 1));
     PA_HIP(B, launch_reduce(lc));
     PA_HIP(B, hipStreamSynchronize(st));  // the host arrays above are now consumed
+    B->class_maps.clear();
     B->host_step.assign(n, 0);
     return PA_OK;
 }
@@ -810,6 +849,72 @@ pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, do
     if (philox_calls) *philox_calls = s.philox_calls;
     if (sweep_words) *sweep_words = s.sweep_words;
     return PA_OK;
+}
+
+static pa_status set_sweep_launch(pa_batch *B, int32_t L, int32_t threads, int32_t gpb,
+                                  int32_t variant) {
+    if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
+    if (threads < 64 || threads > 1024 || threads % 64) return fail(B, PA_ERR_ARG, "threads must be a multiple of 64 in [64, 1024]");
+    if (gpb < 1 || gpb > 8) return fail(B, PA_ERR_ARG, "groups_per_block must be in [1, 8]");
+    if (variant < 0 || variant > 1) return fail(B, PA_ERR_ARG, "variant must be 0 or 1");
+    if (sweep_lds_bytes(L * L, gpb, threads, 1) > (size_t)kMaxSweepLds)
+        return fail(B, PA_ERR_ARG, "groups_per_block * L^2 * 8 plus the word lists exceed the LDS budget");
+    for (size_t k = 0; k < B->lc.sweep_classes.size(); ++k) {
+        SweepClass &sc = B->lc.sweep_classes[k];
+        if (sc.L != L) continue;
+        PA_HIP(B, hipStreamSynchronize(B->stream));
+        sc.threads = threads;
+        sc.gpb = gpb;
+        sc.pooled = variant;
+        pa_status e = upload_class_map(B, (int)k);
+        if (e) return e;
+        PA_HIP(B, hipStreamSynchronize(B->stream));
+        B->class_maps.clear();
+        if (B->exec) {  // the captured graph holds the old geometry
+            (void)hipGraphExecDestroy(B->exec);
+            (void)hipGraphDestroy(B->graph);
+            B->exec = nullptr;
+            B->graph = nullptr;
+        }
+        return PA_OK;
+    }
+    return fail(B, PA_ERR_ARG, "no run with this L");
+}
+
+static pa_status get_sweep_launch(pa_batch *B, int32_t L, int32_t *threads, int32_t *gpb,
+                                  int32_t *variant) {
+    for (const SweepClass &sc : B->lc.sweep_classes) {
+        if (sc.L != L) continue;
+        if (threads) *threads = sc.threads;
+        if (gpb) *gpb = sc.gpb;
+        if (variant) *variant = sc.pooled;
+        return PA_OK;
+    }
+    return fail(B, PA_ERR_ARG, "no run with this L");
+}
+
+pa_status pa_set_sweep_launch(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_block,
+                              int32_t variant) {
+    if (!ctx) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    return set_sweep_launch(&ctx->b, L, threads, groups_per_block, variant);
+}
+
+pa_status pa_get_sweep_launch(pa_ctx *ctx, int32_t L, int32_t *threads, int32_t *groups_per_block,
+                              int32_t *variant) {
+    if (!ctx) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    return get_sweep_launch(&ctx->b, L, threads, groups_per_block, variant);
+}
+
+pa_status pa_batch_set_sweep_launch(pa_batch *b, int32_t L, int32_t threads,
+                                    int32_t groups_per_block, int32_t variant) {
+    if (!b) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    return set_sweep_launch(b, L, threads, groups_per_block, variant);
+}
+
+pa_status pa_batch_get_sweep_launch(pa_batch *b, int32_t L, int32_t *threads,
+                                    int32_t *groups_per_block, int32_t *variant) {
+    if (!b) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    return get_sweep_launch(b, L, threads, groups_per_block, variant);
 }
 
 void pa_destroy(pa_ctx *ctx) {

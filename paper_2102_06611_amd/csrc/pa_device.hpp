@@ -12,6 +12,8 @@ namespace pa {
 constexpr int kLanes = 64;        // replicas per group = bits per multispin word
 constexpr int kSlotBlock = 1024;  // replica slots per block of the per-slot kernels
 constexpr int kMaxL = 128;
+// dynamic LDS available to one sweep block (the static part is 4 KiB)
+constexpr int kMaxSweepLds = 152 * 1024;
 
 // Stream tags in the top nibble of the fourth Philox counter word.
 constexpr uint32_t kTagSweep = 0x10000000u;
@@ -79,6 +81,16 @@ struct WorkMap {
     const int32_t *run_id;     // [n] run index of each entry
 };
 
+// Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// This permutation gives each XCD a contiguous range of blocks, so that
+// neighbouring work items (which share input data) meet in the same L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_swizzle(int b, int total) {
+    const int per = total / kXcds;
+    if (b >= per * kXcds) return b;  // the ragged tail keeps its order
+    return (b % kXcds) * per + b / kXcds;
+}
+
 __device__ inline int map_block(const WorkMap &m, int b, int *item) {
     int lo = 0, hi = m.n - 1;
     while (lo < hi) {  // last entry with blk_off <= b
@@ -95,14 +107,20 @@ __device__ inline int map_block(const WorkMap &m, int b, int *item) {
 // round key; the key advances by a Weyl sequence between rounds.
 struct U4 { uint32_t x, y, z, w; };
 
+// Three-input bitwise functions in one gfx950 instruction (v_bitop3_b32).  The
+// 8-bit table is the function applied to the operand patterns 0xF0, 0xCC, 0xAA.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // 0xF0 ^ 0xCC ^ 0xAA
+}
+
 __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
                                      uint32_t c2, uint32_t c3) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

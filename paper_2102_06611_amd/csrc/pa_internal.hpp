@@ -19,6 +19,9 @@ struct SweepClass {
     WorkMap map;
     int total;
     bool has_msc, has_int8;
+    int threads;  // block size of k_sweep for this lattice size
+    int gpb;      // 64-replica groups per block
+    int pooled;   // 1: undecided words pooled per wavefront; 0: lane-local comparisons
 };
 
 struct LaunchCtx {
@@ -28,11 +31,12 @@ struct LaunchCtx {
     MapInfo slots;   // per run: nblk blocks of kSlotBlock slots
     MapInfo groups;  // per run: G blocks, one per 64-replica group
     std::vector<SweepClass> sweep_classes;  // one launch per distinct L
-    int sweep_threads;
     bool any_nearest, any_multi;
 };
 
 hipError_t configure_kernels();
+size_t sweep_lds_bytes(int N, int gpb, int threads, int cpl);
+int sweep_cpl(int N, int gpb, int threads);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 hipError_t launch_init(const LaunchCtx &c);
 hipError_t launch_sweeps(const LaunchCtx &c, int init);

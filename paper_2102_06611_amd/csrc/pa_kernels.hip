@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
 //    the parents' and the children's rows.
 __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map) {
     int gd;
-    const RunDesc &rd = runs[map_block(map, blockIdx.x, &gd)];
+    const RunDesc &rd = runs[map_block(map, xcd_swizzle(blockIdx.x, gridDim.x), &gd)];
     RunState *st = rd.st;
     if (st->err) return;
     const int Rn = st->R_new, Rp = st->R_cur;
@@ -566,7 +566,57 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
 
 // ------------------------------------------------------------------ Metropolis sweeps
 
-// Bit-sliced Metropolis decision for one word: 64 replicas of one site.  With
+// Bit-sliced Metropolis classes of one word (64 replicas of one site): with
+// a_k = s XOR n_k (antiparallel neighbours), A = sum a_k and dE = 8 - 4A,
+// A >= 2 (dE <= 0) always flips, A = 1 is dE = 4, A = 0 is dE = 8.
+struct WordClass {
+    uint64_t ge2, eq1, eq0;
+};
+__device__ __forceinline__ WordClass classify(uint64_t a1, uint64_t a2, uint64_t a3, uint64_t a4) {
+    const uint64_t x12 = a1 ^ a2, y12 = a1 & a2, x34 = a3 ^ a4, y34 = a3 & a4;
+    const uint64_t ge2 = y12 | y34 | (x12 & x34);
+    const uint64_t any = x12 | y12 | x34 | y34;
+    return WordClass{ge2, any & ~ge2, ~any};
+}
+
+// Two bit planes (one Philox call) of the lazy comparison u32 < T, from the
+// most significant plane down: a lane still tied with its threshold (und) is
+// decided by the first plane where its bit differs from T's bit (T4's for the
+// dE = 4 lanes, T8's for the dE = 8 lanes); it is accepted when the plane bit
+// is 0 and T's is 1.  Returns the newly accepted lanes and updates und.  Per
+// 32-bit half and plane: t = T's bit per lane, accepted = und & t & ~plane,
+// und &= ~(t ^ plane) -- three v_bitop3 and one OR.  On the lanes still tied
+// the dE = 8 lanes are exactly those not in eq1, so t = eq1 ? T4-bit : T8-bit
+// there; elsewhere t does not matter.
+__device__ __forceinline__ uint32_t plane_bits(uint32_t &und, uint32_t eq1, uint32_t m4,
+                                               uint32_t m8, uint32_t pl) {
+    const uint32_t t = __builtin_amdgcn_bitop3_b32(eq1, m4, m8, 0xCA);    // eq1 ? m4 : m8
+    const uint32_t acc = __builtin_amdgcn_bitop3_b32(und, t, pl, 0x40);  // und & t & ~pl
+    und = __builtin_amdgcn_bitop3_b32(und, t, pl, 0x90);                 // und & ~(t ^ pl)
+    return acc;
+}
+
+__device__ __forceinline__ uint64_t planes_step(uint64_t &und, uint64_t eq1, uint32_t T4,
+                                                uint32_t T8, uint32_t p, const U4 &x) {
+    const uint32_t sa = 31u - 2u * p, sb = 30u - 2u * p;
+    const uint32_t m4a = 0u - ((T4 >> sa) & 1u), m8a = 0u - ((T8 >> sa) & 1u);
+    const uint32_t m4b = 0u - ((T4 >> sb) & 1u), m8b = 0u - ((T8 >> sb) & 1u);
+    uint32_t ul = (uint32_t)und, uh = (uint32_t)(und >> 32);
+    const uint32_t el = (uint32_t)eq1, eh = (uint32_t)(eq1 >> 32);
+    uint32_t al = plane_bits(ul, el, m4a, m8a, x.x);
+    uint32_t ah = plane_bits(uh, eh, m4a, m8a, x.y);
+    al |= plane_bits(ul, el, m4b, m8b, x.z);
+    ah |= plane_bits(uh, eh, m4b, m8b, x.w);
+    und = ((uint64_t)uh << 32) | ul;
+    return ((uint64_t)ah << 32) | al;
+}
+
+__device__ __forceinline__ uint64_t plane_pair(uint64_t &und, uint64_t eq1, uint32_t T4, uint32_t T8,
+                                               uint32_t p, const U4 &x) {
+    return planes_step(und, eq1, T4, T8, p, x);
+}
+
+// Lane-local variant: the whole lazy comparison of one word in its own lane.  With
 // a_k = s XOR n_k (antiparallel neighbours), A = sum a_k and dE = 8 - 4A:
 // A >= 2 (dE <= 0) always flips; A = 1 (dE = 4) and A = 0 (dE = 8) flip iff
 // u32 < t4 / t8.  u32 is compared bit plane by bit plane from the most
@@ -594,57 +644,84 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
     uint32_t p = 0;
     for (; und != 0 && p < 16; ++p) {
-        U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
-        const uint64_t pa = ((uint64_t)x.y << 32) | x.x;
-        const uint64_t pb = ((uint64_t)x.w << 32) | x.z;
-        const uint32_t sa = 31u - 2u * p, sb = 30u - 2u * p;
-        // t = threshold bit of each lane: T4's bit for dE = 4 lanes, T8's for dE = 8
-        const uint64_t m4a = 0ull - (uint64_t)((T4 >> sa) & 1u), m8a = 0ull - (uint64_t)((T8 >> sa) & 1u);
-        const uint64_t m4b = 0ull - (uint64_t)((T4 >> sb) & 1u), m8b = 0ull - (uint64_t)((T8 >> sb) & 1u);
-        uint64_t t = (eq1 & m4a) | (eq0 & m8a);
-        uint64_t d = pa ^ t;          // lanes decided by this plane
-        flip |= und & d & t;          // ... in favour of u < T
-        und &= ~d;
-        t = (eq1 & m4b) | (eq0 & m8b);
-        d = pb ^ t;
-        flip |= und & d & t;
-        und &= ~d;
+        const U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
+        flip |= planes_step(und, eq1, T4, T8, p, x);
     }
     *calls += p;
     return flip;
 }
 
-// One block per (run, group): the group's L x L x 64 lattice lives in LDS as
-// N words for all theta sweeps (colour 0 then colour 1; a site's index within
-// its colour w = y L/2 + floor(x/2) and the global half-sweep index
-// h = 2 (theta (i-1) + sweep) + colour key its random planes).  Afterwards
-// each replica's E = 2U - 2N (U antiparallel bonds) and M are measured.
-// With init != 0 no sweep is done (measurement of the beta_0 population).
-template <int LAYOUT>
-__global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map, int init) {
+// Position of a word of one colour inside the block's lattices: word index
+// idx -> (group gl, row y, half-column xh), lattice offsets of the site and its
+// four neighbours (reciprocal multiply with a one-step correction).
+struct WordPos {
+    int gl, wi, site, r, l, u, d;
+};
+__device__ __forceinline__ WordPos word_pos(int idx, int colour, int L, int N, int half,
+                                            float inv_half, float inv_L) {
+    int r = (int)((float)idx * inv_half);
+    int xh = idx - r * half;
+    if (xh >= half) { ++r; xh -= half; }
+    if (xh < 0) { --r; xh += half; }
+    int gl = (int)((float)r * inv_L);
+    int y = r - gl * L;
+    if (y >= L) { ++gl; y -= L; }
+    if (y < 0) { --gl; y += L; }
+    const int x = 2 * xh + ((colour + y) & 1);
+    const int base = gl * N;
+    const int row = base + y * L;
+    WordPos w;
+    w.gl = gl;
+    w.wi = y * half + xh;
+    w.site = row + x;
+    w.r = row + ((x == L - 1) ? 0 : x + 1);
+    w.l = row + ((x == 0) ? L - 1 : x - 1);
+    w.u = ((y == 0) ? base + N - L : row - L) + x;
+    w.d = ((y == L - 1) ? base : row + L) + x;
+    return w;
+}
+
+// One block per (run, gpb consecutive groups): the groups' L x L x 64
+// lattices live in LDS as gpb * N words for all theta sweeps (colour 0 then
+// colour 1; a site's index within its colour w = y L/2 + floor(x/2) and the
+// global half-sweep index h = 2 (theta (i-1) + sweep) + colour key its random
+// planes).  A half-sweep takes its words in batches of cpl per lane: every
+// word first gets up to kPhaseA Philox calls in its own lane; the words with
+// lanes still tied go to a per-wavefront list, which all 64 lanes then work
+// through one plane pair per round, so that the few long comparisons do not
+// hold up a whole wavefront.  Afterwards each replica's E = 2U - 2N (U
+// antiparallel bonds) and M are measured.  With init != 0 no sweep is done.
+constexpr int kMaxGroupsPerBlock = 8;
+
+constexpr uint32_t kPhaseA = 3;  // Philox calls per word before a word is listed
+
+template <int LAYOUT, int POOLED>
+__global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map, int init,
+                                                int gpb, int cpl) {
     extern __shared__ uint64_t lat[];
-    __shared__ int32_t red_u[kLanes], red_up[kLanes];
-    int g;
-    const RunDesc &rd = runs[map_block(map, blockIdx.x, &g)];
+    __shared__ int32_t red_u[kMaxGroupsPerBlock * kLanes], red_up[kMaxGroupsPerBlock * kLanes];
+    int bi;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &bi)];
     RunState *st = rd.st;
     if (rd.layout != LAYOUT || st->err) return;
     const int Rn = st->R_new;
-    if (g * kLanes >= Rn) return;
+    const int g0 = bi * gpb;
+    if (g0 * kLanes >= Rn) return;
+    const int ng = min(gpb, (Rn + kLanes - 1) / kLanes - g0);  // groups with live replicas
     const int L = rd.L, N = rd.N, half = L >> 1, nb = st->cur ^ 1;
-    const uint64_t valid = lane_mask(Rn - g * kLanes);
     const int tid = threadIdx.x, nt = blockDim.x;
 
     if (LAYOUT == PA_LAYOUT_MSC64) {
-        const uint64_t *src = rd.ms[nb] + (size_t)g * N;
-        for (int w = tid; w < N; w += nt) lat[w] = src[w];
+        const uint64_t *src = rd.ms[nb] + (size_t)g0 * N;
+        for (int w = tid; w < ng * N; w += nt) lat[w] = src[w];
     } else {
-        const uint4 *src = reinterpret_cast<const uint4 *>(rd.s8[nb] + (size_t)g * N * kLanes);
+        const uint4 *src = reinterpret_cast<const uint4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes);
         uint16_t *l16 = reinterpret_cast<uint16_t *>(lat);
-        for (int it = tid; it < N * 4; it += nt) l16[it] = (uint16_t)pack16(src[it]);
+        for (int it = tid; it < ng * N * 4; it += nt) l16[it] = (uint16_t)pack16(src[it]);
     }
-    if (tid < kLanes) {
-        red_u[tid] = 0;
-        red_up[tid] = 0;
+    for (int k = tid; k < ng * kLanes; k += nt) {
+        red_u[k] = 0;
+        red_up[k] = 0;
     }
     __syncthreads();
 
@@ -652,39 +729,127 @@ __global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map,
     const int i = st->step + 1;
     const uint64_t t4 = st->t4, t8 = st->t8;
     const bool all4 = t4 >= (1ull << 32), all8 = t8 >= (1ull << 32);
-    const float inv_half = 1.0f / (float)half;
+    // threshold bits are the same for every lane: keep them in scalar registers
+    const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
+    const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
+    const float inv_half = 1.0f / (float)half, inv_L = 1.0f / (float)L;
+    const int words = ng * (N >> 1);  // sites of one colour, all groups of the block
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    // per-wavefront lists of undecided words (two, used alternately): word
+    // index and the mask of still undecided lanes
+    const int cap = cpl * kLanes;
+    uint64_t *und_list = lat + (size_t)gpb * N + (size_t)wave * 2 * cap;
+    uint16_t *idx_list = reinterpret_cast<uint16_t *>(lat + (size_t)gpb * N + (size_t)nw * 2 * cap) +
+                         (size_t)wave * 2 * cap;
+    const uint32_t k0 = rd.key0, k1 = rd.key1;
     uint32_t calls = 0;
     for (int s = 0; s < theta; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
-            for (int wi = tid; wi < (N >> 1); wi += nt) {
-                int y = (int)((float)wi * inv_half);
-                int xh = wi - y * half;
-                if (xh >= half) { ++y; xh -= half; }
-                if (xh < 0) { --y; xh += half; }
-                const int x = 2 * xh + ((colour + y) & 1);
-                const int row = y * L;
-                const int up = (y == 0) ? N - L : row - L;
-                const int dn = (y == L - 1) ? 0 : row + L;
-                const int xl = (x == 0) ? L - 1 : x - 1;
-                const int xr = (x == L - 1) ? 0 : x + 1;
-                const uint64_t s0 = lat[row + x];
-                const uint64_t f = metropolis_word(s0 ^ lat[row + xr], s0 ^ lat[row + xl],
-                                                   s0 ^ lat[up + x], s0 ^ lat[dn + x], valid, t4,
-                                                   t8, all4, all8, rd.key0, rd.key1,
-                                                   (uint32_t)wi, (uint32_t)g, h, &calls);
-                lat[row + x] = s0 ^ f;
+            if (!POOLED) {
+                // lane-local: each word's comparison runs to the end in its lane
+                for (int idx = tid; idx < words; idx += nt) {
+                    const WordPos w = word_pos(idx, colour, L, N, half, inv_half, inv_L);
+                    const int g = g0 + w.gl;
+                    const uint64_t s0 = lat[w.site];
+                    const uint64_t f = metropolis_word(s0 ^ lat[w.r], s0 ^ lat[w.l], s0 ^ lat[w.u],
+                                                       s0 ^ lat[w.d], lane_mask(Rn - g * kLanes), t4,
+                                                       t8, all4, all8, k0, k1, (uint32_t)w.wi,
+                                                       (uint32_t)g, h, &calls);
+                    lat[w.site] = s0 ^ f;
+                }
+                __syncthreads();
+                continue;
+            }
+            for (int b0 = 0; b0 < words; b0 += cpl * nt) {
+                // phase A: each lane takes cpl words and spends up to kPhaseA
+                // Philox calls on each; still undecided words go to the list
+                int cnt = 0;
+                for (int k = 0; k < cpl; ++k) {
+                    const int idx = b0 + wave * cap + k * kLanes + lane;
+                    const bool active = idx < words;
+                    uint64_t und = 0;
+                    if (active) {
+                        const WordPos w = word_pos(idx, colour, L, N, half, inv_half, inv_L);
+                        const int g = g0 + w.gl;
+                        const uint64_t valid = lane_mask(Rn - g * kLanes);
+                        const uint64_t s0 = lat[w.site];
+                        WordClass c = classify(s0 ^ lat[w.r], s0 ^ lat[w.l], s0 ^ lat[w.u], s0 ^ lat[w.d]);
+                        uint64_t flip = c.ge2;
+                        if (all4) { flip |= c.eq1; c.eq1 = 0; }
+                        if (all8) { flip |= c.eq0; c.eq0 = 0; }
+                        flip &= valid;
+                        c.eq1 &= valid;
+                        und = (c.eq1 | c.eq0) & valid;
+#pragma unroll
+                        for (uint32_t p = 0; p < kPhaseA; ++p) {
+                            if (und) {
+                                const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagSweep | p);
+                                flip |= plane_pair(und, c.eq1, T4, T8, p, x);
+                                ++calls;
+                            }
+                        }
+                        lat[w.site] = s0 ^ flip;
+                    }
+                    const bool pend = active && und != 0;
+                    const uint64_t m = __ballot(pend);
+                    if (pend) {
+                        const int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+                        idx_list[pos] = (uint16_t)idx;
+                        und_list[pos] = und;
+                    }
+                    cnt += __popcll(m);
+                }
+                // phase B: one plane pair per round for every listed word, all
+                // lanes of the wavefront working on the list
+                int cur = 0;
+                for (uint32_t p = kPhaseA; cnt > 0 && p < 16; ++p) {
+                    int next = 0;
+                    for (int base = 0; base < cnt; base += kLanes) {
+                        const int e = base + lane;
+                        const bool act = e < cnt;
+                        uint64_t und = 0;
+                        int idx = 0;
+                        if (act) {
+                            idx = idx_list[cur * cap + e];
+                            und = und_list[cur * cap + e];
+                            const WordPos w = word_pos(idx, colour, L, N, half, inv_half, inv_L);
+                            const int g = g0 + w.gl;
+                            // undecided lanes still hold their original spin, so
+                            // their classes can be recomputed from the lattice
+                            const uint64_t s0 = lat[w.site];
+                            const WordClass c = classify(s0 ^ lat[w.r], s0 ^ lat[w.l], s0 ^ lat[w.u],
+                                                         s0 ^ lat[w.d]);
+                            const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagSweep | p);
+                            const uint64_t acc = plane_pair(und, c.eq1 & und, T4, T8, p, x);
+                            ++calls;
+                            if (acc) lat[w.site] = s0 ^ acc;
+                        }
+                        const bool pend = act && und != 0;
+                        const uint64_t m = __ballot(pend);
+                        if (pend) {
+                            const int pos = next + __popcll(m & ((1ull << lane) - 1ull));
+                            idx_list[(cur ^ 1) * cap + pos] = (uint16_t)idx;
+                            und_list[(cur ^ 1) * cap + pos] = und;
+                        }
+                        next += __popcll(m);
+                    }
+                    cur ^= 1;
+                    cnt = next;
+                }
+                // lanes still tied after 32 planes have u32 == T: rejected
             }
             __syncthreads();
         }
     }
 
-    // measurement: lane = replica; waves split the rows
+    // measurement: lane = replica; waves split the (group, row) pairs
     {
         const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-        int U = 0, upc = 0;
-        for (int y = wave; y < L; y += nw) {
-            const int row = y * L, dn = (y == L - 1) ? 0 : row + L;
+        for (int q = wave; q < ng * L; q += nw) {
+            const int gl = q / L, y = q - gl * L;
+            const int base = gl * N, row = base + y * L, dn = (y == L - 1) ? base : row + L;
+            int U = 0, upc = 0;
             for (int x = 0; x < L; ++x) {
                 const uint64_t w0 = lat[row + x];
                 const uint64_t wr = lat[row + ((x == L - 1) ? 0 : x + 1)];
@@ -692,32 +857,32 @@ __global__ void __launch_bounds__(256) k_sweep(const RunDesc *runs, WorkMap map,
                 U += (int)(((w0 ^ wr) >> lane) & 1ull) + (int)(((w0 ^ wd) >> lane) & 1ull);
                 upc += (int)((w0 >> lane) & 1ull);
             }
+            atomicAdd(&red_u[gl * kLanes + lane], U);
+            atomicAdd(&red_up[gl * kLanes + lane], upc);
         }
-        atomicAdd(&red_u[lane], U);
-        atomicAdd(&red_up[lane], upc);
     }
     {  // Philox calls of this block (one atomic per wave)
-        uint64_t c64 = wave_sum_i64((int64_t)calls);
+        const uint64_t c64 = wave_sum_i64((int64_t)calls);
         if ((tid & 63) == 0 && theta > 0) atomicAdd(&st->philox_calls, (unsigned long long)c64);
         if (tid == 0 && theta > 0)
-            atomicAdd(&st->sweep_words, (unsigned long long)theta * (unsigned long long)N);
+            atomicAdd(&st->sweep_words, (unsigned long long)theta * (unsigned long long)N * ng);
     }
     __syncthreads();
-    if (tid < kLanes) {
-        const int c = g * kLanes + tid;
+    for (int k = tid; k < ng * kLanes; k += nt) {
+        const int c = g0 * kLanes + k;
         if (c < Rn) {
-            rd.E[c] = 2 * red_u[tid] - 2 * N;
-            rd.M[c] = 2 * red_up[tid] - N;
+            rd.E[c] = 2 * red_u[k] - 2 * N;
+            rd.M[c] = 2 * red_up[k] - N;
         }
     }
     if (theta > 0) {
         if (LAYOUT == PA_LAYOUT_MSC64) {
-            uint64_t *dst = rd.ms[nb] + (size_t)g * N;
-            for (int w = tid; w < N; w += nt) dst[w] = lat[w];
+            uint64_t *dst = rd.ms[nb] + (size_t)g0 * N;
+            for (int w = tid; w < ng * N; w += nt) dst[w] = lat[w];
         } else {
-            uint4 *dst = reinterpret_cast<uint4 *>(rd.s8[nb] + (size_t)g * N * kLanes);
+            uint4 *dst = reinterpret_cast<uint4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes);
             const uint16_t *l16 = reinterpret_cast<const uint16_t *>(lat);
-            for (int it = tid; it < N * 4; it += nt) dst[it] = unpack16(l16[it]);
+            for (int it = tid; it < ng * N * 4; it += nt) dst[it] = unpack16(l16[it]);
         }
     }
 }
@@ -989,15 +1154,37 @@ hipError_t launch_init(const LaunchCtx &c) {
     return hipSuccess;
 }
 
+size_t sweep_lds_bytes(int N, int gpb, int threads, int cpl) {
+    return (size_t)gpb * N * 8 + (size_t)(threads / 64) * 2 * cpl * kLanes * (8 + 2);
+}
+
+// words per lane per batch: as many as the LDS left beside the lattices allows (<= 4)
+int sweep_cpl(int N, int gpb, int threads) {
+    for (int cpl = 4; cpl > 1; --cpl)
+        if (sweep_lds_bytes(N, gpb, threads, cpl) <= (size_t)kMaxSweepLds) return cpl;
+    return 1;
+}
+
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
     for (const auto &cls : c.sweep_classes) {
-        size_t lds = (size_t)cls.N * sizeof(uint64_t);
-        if (cls.has_msc)
-            PA_LAUNCH(k_sweep<PA_LAYOUT_MSC64>, dim3(cls.total), dim3(c.sweep_threads), lds,
-                      c.stream, c.runs, cls.map, init);
-        if (cls.has_int8)
-            PA_LAUNCH(k_sweep<PA_LAYOUT_INT8>, dim3(cls.total), dim3(c.sweep_threads), lds,
-                      c.stream, c.runs, cls.map, init);
+        const int cpl = cls.pooled ? sweep_cpl(cls.N, cls.gpb, cls.threads) : 0;
+        const size_t lds = sweep_lds_bytes(cls.N, cls.gpb, cls.threads, cpl);
+        if (cls.has_msc) {
+            if (cls.pooled)
+                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, 1>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
+            else
+                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, 0>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
+        }
+        if (cls.has_int8) {
+            if (cls.pooled)
+                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, 1>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
+            else
+                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, 0>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
+        }
     }
     return hipSuccess;
 }
@@ -1093,14 +1280,14 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 }
 
 hipError_t configure_kernels() {
-    // the L = 128 lattice (16384 words) needs 128 KiB of LDS per block
-    hipError_t e = hipFuncSetAttribute((const void *)k_sweep<PA_LAYOUT_MSC64>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxL * kMaxL * (int)sizeof(uint64_t));
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_sweep<PA_LAYOUT_INT8>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kMaxL * kMaxL * (int)sizeof(uint64_t));
+    // up to kMaxSweepLds bytes of lattice (+ word lists) per block
+    const void *fns[4] = {(const void *)k_sweep<PA_LAYOUT_MSC64, 0>, (const void *)k_sweep<PA_LAYOUT_MSC64, 1>,
+                          (const void *)k_sweep<PA_LAYOUT_INT8, 0>, (const void *)k_sweep<PA_LAYOUT_INT8, 1>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace pa

@@ -220,3 +220,28 @@ def test_learned_schedule_runs_and_logs():
     X, t = schedules.training_rows(run)
     assert X.shape[0] == t.shape[0] <= n and torch.isfinite(t).all()
     run.close()
+
+
+def test_sweep_geometry_does_not_change_results():
+    betas = linear_schedule(0.5, 4)
+    states = []
+    for threads, gpb, variant in ((256, 4, 0), (64, 1, 1), (1024, 2, 0), (128, 8, 1), (512, 1, 1)):
+        r = pa.Run(16, 1000, betas, 3, 61, "nearest", "msc64")
+        r.set_sweep_launch(16, threads, gpb, variant)
+        assert r.sweep_launch(16) == (threads, gpb, variant)
+        r.run(4)
+        states.append(r.get_state())
+        r.close()
+    assert all(s == states[0] for s in states)
+
+
+def test_autotuner_times_candidates_and_keeps_results():
+    from paper_2102_06611_amd import autotune
+    betas = linear_schedule(0.44, 10)
+    run = pa.Run(32, 3000, betas, 4, 62, "multinomial", "int8")
+    for _ in range(3):
+        run.anneal_step()
+    best, results = autotune.tune_run(run, 32, steps=1)
+    assert len(results) == len(autotune.candidates(32)) and best == min(results)
+    assert run.sweep_launch(32) == (best[1], best[2], best[3])
+    run.close()
