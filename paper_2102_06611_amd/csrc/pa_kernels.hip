@@ -186,29 +186,30 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
                 st->err = PA_ERR_ARG;
                 st->err_step = i;
                 ok = 0;
-            } else if (b1 == 0.0) {
-                st->t4 = st->t8 = 1ull << 32;
-            } else {
-                dd p4;
-                bool amb = false;
-                if (!dd_exp_neg(dd{4.0 * b1, 0.0}, &p4)) {
-                    st->t4 = st->t8 = 1;  // 0 < p < 2^-1000
-                } else {
-                    const dd p8 = dd_mul(p4, p4);  // e^{-8 beta} = (e^{-4 beta})^2
-                    st->t4 = dd_ceil_decided(dd_ldexp(p4, 32), &amb);
-                    st->t8 = p8.hi < 0x1p-990 ? 1 : dd_ceil_decided(dd_ldexp(p8, 32), &amb);
-                }
-                if (amb) {
-                    st->err = PA_ERR_NUMERIC;
-                    st->err_step = i;
-                    ok = 0;
-                }
             }
         }
         st->sum_cnt2 = 0;
     }
     __syncthreads();
     if (!ok) return;
+    const int last = blockDim.x - 1;  // computes the thresholds and ln Q beside its levels
+    if (threadIdx.x == last) {
+        const double b1 = rd.betas[i];
+        if (b1 == 0.0) {
+            st->t4 = st->t8 = 1ull << 32;
+        } else {
+            dd p4;
+            bool amb = false;
+            if (!dd_exp_neg(dd{4.0 * b1, 0.0}, &p4)) {
+                st->t4 = st->t8 = 1;  // 0 < p < 2^-1000
+            } else {
+                const dd p8 = dd_mul(p4, p4);  // e^{-8 beta} = (e^{-4 beta})^2
+                st->t4 = dd_ceil_decided(dd_ldexp(p4, 32), &amb);
+                st->t8 = p8.hi < 0x1p-990 ? 1 : dd_ceil_decided(dd_ldexp(p8, 32), &amb);
+            }
+            if (amb) atomicOr(&amb_any, 1);
+        }
+    }
     const int Rp = st->R_cur, kmin = st->kmin, kmax = st->kmax;
     const int nlev = kmax - kmin + 1;
     const dd db = two_sum(rd.betas[i], -rd.betas[i - 1]);
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
         __syncthreads();
     }
     const dd S{sh_hi[0], sh_lo[0]};
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == last) {
         const double e_min = -2.0 * rd.N + 4.0 * kmin;
         dd lnq;
         if (exact && db.hi == 0.0) {
@@ -388,23 +389,42 @@ __global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap 
 
 // Multinomial, pass 3: draw d (of R) picks the first parent with
 // cum > floor(U64_d * W / 2^64); counts accumulate atomically (order-free).
+// The search first runs over every 64th cumulative weight, held in LDS, and
+// then over the at most 64 parents of the chosen stretch.
+constexpr int kCoarse = 4096;
+
 __global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
     if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    __shared__ uint64_t coarse[kCoarse];
     const int Rp = st->R_cur, i = st->step + 1;
     const uint64_t W = st->w_total;
+    const int nc = (Rp + 63) >> 6;  // stretch k covers parents [64k, 64k + 63]
+    const bool use_coarse = nc <= kCoarse;
+    if (use_coarse)
+        for (int k = threadIdx.x; k < nc; k += blockDim.x) coarse[k] = rd.cum[min(64 * k + 63, Rp - 1)];
+    __syncthreads();
     const int d0 = b * kSlotBlock + 4 * (int)threadIdx.x;
     for (int h = 0; h < 2; ++h) {
         const int d = d0 + 2 * h;
         if (d >= rd.R) break;
-        U4 x = philox(rd.key0, rd.key1, (uint32_t)(d >> 1), (uint32_t)i, 0u, kTagMulti);
+        const U4 x = philox(rd.key0, rd.key1, (uint32_t)(d >> 1), (uint32_t)i, 0u, kTagMulti);
         const uint64_t U[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
         for (int m = 0; m < 2; ++m) {
             if (d + m >= rd.R) break;
             const uint64_t target = mulhi64(U[m], W);
             int lo = 0, hi = Rp - 1;  // first j with cum[j] > target
+            if (use_coarse) {
+                int cl = 0, ch = nc - 1;  // first stretch whose last weight exceeds target
+                while (cl < ch) {
+                    const int mid = (cl + ch) >> 1;
+                    if (coarse[mid] > target) ch = mid; else cl = mid + 1;
+                }
+                lo = 64 * cl;
+                hi = min(64 * cl + 63, Rp - 1);
+            }
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (rd.cum[mid] > target) hi = mid; else lo = mid + 1;

@@ -98,3 +98,84 @@ def train(X, t, iters: int = 3000, lr: float = 3e-3, seed: int = 0,
         if k % 100 == 0 or k == 1:
             losses.append(float(loss.item()))
     return params, losses
+
+
+def collect(Ls, R: int, seeds, theta: int, alpha: float, beta_final: float, max_steps: int = 4000,
+            stream=None):
+    """Training rows from adaptive runs: one row per temperature step."""
+    import torch
+    Xs, ts = [], []
+    for L in Ls:
+        for s in seeds:
+            run = adaptive_run(L, R, theta, s, alpha, beta_final, max_steps, stream=stream)
+            X, t = training_rows(run)
+            Xs.append(X)
+            ts.append(t)
+            run.close()
+    return torch.cat(Xs).contiguous(), torch.cat(ts).contiguous()
+
+
+def compare(params, L: int, R: int, theta: int, seeds, ln_z_final: float, alpha: float = 0.85,
+            alpha_min: float = 0.80, beta_final: float = 1.0, max_steps: int = 4000):
+    """Plain adaptive vs learned schedule on the same seeds.
+
+    Returns one dict per seed: steps to reach beta_final and the free-energy
+    error |(-beta F) - ln Z_exact| / L^2 at beta_final for both, and the
+    fraction of learned proposals that passed the overlap guard.
+    """
+    out = []
+    N = L * L
+    for s in seeds:
+        a = adaptive_run(L, R, theta, s, alpha, beta_final, max_steps)
+        na = a.current()[0]
+        ea = abs(a.observables(na)["minus_beta_F"] - ln_z_final) / N
+        a.close()
+        lr = learned_run(params, L, R, theta, s, alpha_min, alpha, beta_final, max_steps)
+        nl = lr.current()[0]
+        el = abs(lr.observables(nl)["minus_beta_F"] - ln_z_final) / N
+        _, acc, alpha_taken = lr.schedule_log()
+        lr.close()
+        out.append({"seed": s, "steps_adaptive": na, "error_adaptive": ea, "steps_learned": nl,
+                    "error_learned": el, "accepted": float(np.mean(acc)) if len(acc) else 0.0,
+                    "alpha_mean_learned": float(np.mean(alpha_taken)) if len(alpha_taken) else 0.0})
+    return out
+
+
+def main(argv=None):
+    """Train on adaptive runs at L = 32 and 64 (R = 20000) and compare the learned
+    schedule with the plain adaptive one at L = 128, R = 100000, beta 0 -> 1.0.
+
+        python -m paper_2102_06611_amd.schedules [--quick]
+    """
+    import argparse
+    import json
+    import os
+    import time
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="smaller lattices and populations")
+    ap.add_argument("--ln-z", type=float, default=None,
+                    help="exact ln Z at beta_final for the evaluation lattice")
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    if args.quick:
+        train_L, train_R, eval_L, eval_R, seeds = (16, 32), 5000, 32, 5000, range(4)
+    else:
+        train_L, train_R, eval_L, eval_R, seeds = (32, 64), 20000, 128, 100000, range(3)
+    X, t = collect(train_L, train_R, range(500, 506), 10, 0.85, 1.0)
+    params, losses = train(X, t, iters=4000, lr=2e-3)
+    ln_z = args.ln_z
+    if ln_z is None:
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        pts = json.load(open(os.path.join(root, "tests", "golden", "exact_lnz.json")))["points"]
+        ln_z = pts["L%d_1" % eval_L]
+    res = compare(params, eval_L, eval_R, 10, [900 + s for s in seeds], ln_z)
+    print(json.dumps({"train": {"L": list(train_L), "R": train_R, "rows": int(X.shape[0]),
+                                "loss_first": losses[0], "loss_last": losses[-1]},
+                      "eval": {"L": eval_L, "R": eval_R, "alpha": 0.85, "alpha_min": 0.80},
+                      "runs": res, "seconds": time.time() - t0}))
+
+
+if __name__ == "__main__":
+    main()
