@@ -13,7 +13,6 @@ headline.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -39,14 +38,6 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("pa_kernels.hip", "pa_device.hpp", "pa_block.hpp"):
-        with open(os.path.join(ROOT, "paper_2102_06611_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kernel: str):
     """FETCH/WRITE bytes per launch from profiles/traffic.json, if taken on this source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -54,8 +45,9 @@ def measured_traffic(kernel: str):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
+    from paper_2102_06611_amd.counters import source_hash
     e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != source_hash():
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -146,6 +138,18 @@ def cpu_baseline(betas, energies):
             "resample_s_per_step": t_res, "sweep_seconds": t_sweep}
 
 
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, three times: the reference that
+    scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copied 3 x 1 GiB")
+
+
 def head_candidate(layouts: str) -> str:
     names = layouts.split(",")
     return "msc64" if "msc64" in names else names[0]
@@ -159,7 +163,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layouts", default="msc64,int8")
     ap.add_argument("--headline-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB on the device three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs one population per device and "
               "uses no collectives; run with --gpus 1", file=sys.stderr)

@@ -174,8 +174,8 @@ pa_status pa_set_population(pa_ctx *ctx, int32_t step, int32_t R_i, const int8_t
 pa_status pa_overlap(pa_ctx *ctx, double dbeta, double *alpha);
 
 /* Largest dbeta in (0, dbeta_max] with alpha(beta_i, beta_i + dbeta) >= alpha
- * _target, by bisection on the device (dbeta_max if that already qualifies).
- * Synchronises. */
+ * _target, by a 17-ary bracket search on the device to within dbeta_max
+ * 2^-49 (dbeta_max if that already qualifies).  Synchronises. */
 pa_status pa_adaptive_dbeta(pa_ctx *ctx, double alpha_target, double dbeta_max, double *dbeta);
 
 /* Phase timing.  While enabled, every step records HIP events on the run's
@@ -285,7 +285,8 @@ pa_status pa_anneal_step_learned(pa_ctx *ctx, const float *dev_params, double al
 /* Per-step log of the device-chosen schedule, for steps 1..n (n = current
  * step): the features of the population that entered step i
  * (dev_feat[35 (i - 1) ..]), the training target log(dbeta*_i sigma_E)
- * (dev_target[i - 1]), whether the learned proposal was taken (accepted[i -
+ * (dev_target[i - 1]; NaN on learned steps whose proposal was taken, where
+ * dbeta* is not searched for), whether the learned proposal was taken (accepted[i -
  * 1], host) and the overlap of the step actually taken (alpha[i - 1], host).
  * Rows of steps not chosen on the device are zero.  Any output may be NULL;
  * cap bounds the rows written.  Synchronises. */
@@ -296,7 +297,8 @@ pa_status pa_schedule_log(pa_ctx *ctx, float *dev_feat, float *dev_target, int32
  * current population, y = MLP(features), proposal dbeta = exp(y) / sigma_E
  * clipped to (0, dbeta_max]; accepted (*accepted = 1) iff alpha(beta_i,
  * beta_i + dbeta) >= alpha_min, otherwise replaced by pa_adaptive_dbeta's
- * answer for alpha_target (*accepted = 0).  dev_feat (35 floats, may be NULL)
+ * answer for alpha_target (*accepted = 0); dbeta* is searched for only when
+ * the proposal is rejected.  dev_feat (35 floats, may be NULL)
  * receives the features.  Synchronises. */
 pa_status pa_learned_dbeta(pa_ctx *ctx, const float *dev_params, double alpha_min,
                            double alpha_target, double dbeta_max, float *dev_feat,

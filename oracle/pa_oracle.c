@@ -61,16 +61,22 @@ void oracle_philox4x32_10(uint32_t key0, uint32_t key1, const uint32_t ctr[4], u
  * stream tag in its top nibble.  Replica slot r belongs to group g = r / 64
  * and is lane r % 64 of that group.
  *   INIT     (site, g, 0, 0x2000_0000): bits x0 | x1<<32, bit lane = 1 -> +1
- *   SWEEP    (w, g, h, 0x1000_0000 | p), p = 0..15: planes 2p = x0 | x1<<32
- *            and 2p+1 = x2 | x3<<32; the uniform of lane l is the 32-bit
- *            integer whose bit (31 - b) is bit l of plane b.  w is the site's
- *            index within its colour, h the global half-sweep index.
+ *   SWEEP    (w, g, h, 0x1000_0000 | p), p = 0, 1, 2: bit planes 2p =
+ *            x0 | x1<<32 and 2p+1 = x2 | x3<<32.  Bit (31 - b) of the uniform of
+ *            lane l is bit l of plane b, for b < 6.  w is the site's index within
+ *            its colour, h the global half-sweep index.
+ *   TIE      (w, g, h, 0x1000_0100 | q): the lanes of a word whose top six
+ *            bits equal those of their threshold are its ties; the k-th tie in
+ *            ascending lane order takes word k & 3 of call q = k >> 2, shifted
+ *            right by six, as its low 26 bits.  Other lanes' low bits are 0: their
+ *            comparison is already decided by the top six.
  *   RESAMPLE (j >> 2, i, 0, 0x3000_0000): the uniform of parent j at step i
  *            is output word j & 3.
  *   MULTI    (d >> 1, i, 0, 0x4000_0000): the 64-bit uniform of draw d at
  *            step i is x0 | x1<<32 (d even) or x2 | x3<<32 (d odd).
  */
 #define TAG_SWEEP 0x10000000u
+#define TAG_TIE 0x10000100u
 #define TAG_INIT 0x20000000u
 #define TAG_RESAMPLE 0x30000000u
 #define TAG_MULTI 0x40000000u
@@ -80,19 +86,46 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
     oracle_philox4x32_10((uint32_t)seed, (uint32_t)(seed >> 32), ctr, out);
 }
 
-uint32_t oracle_sweep_uniform(uint64_t seed, uint32_t w, uint32_t g, uint32_t h, uint32_t lane) {
-    uint32_t u = 0;
-    for (uint32_t p = 0; p < 16; ++p) {
+/* The top six bits of lane l's Metropolis uniform in word (w, g, h). */
+uint32_t oracle_sweep_top6(uint64_t seed, uint32_t w, uint32_t g, uint32_t h, uint32_t lane) {
+    uint32_t top = 0;
+    for (uint32_t p = 0; p < 3; ++p) {
         uint32_t x[4];
         draw(seed, w, g, h, TAG_SWEEP | p, x);
         uint64_t plane_a = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
         uint64_t plane_b = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
-        uint32_t bit_a = (uint32_t)((plane_a >> lane) & 1u);
-        uint32_t bit_b = (uint32_t)((plane_b >> lane) & 1u);
-        u |= bit_a << (31u - 2u * p);
-        u |= bit_b << (30u - 2u * p);
+        top |= (uint32_t)((plane_a >> lane) & 1u) << (5u - 2u * p);
+        top |= (uint32_t)((plane_b >> lane) & 1u) << (4u - 2u * p);
     }
-    return u;
+    return top;
+}
+
+/*
+ * The Metropolis uniforms u[l] of the 64 lanes of word (w, g, h).  needs[l]
+ * says whether lane l compares a uniform with a threshold at all (a valid
+ * replica with dE > 0 whose threshold thr[l] is below 2^32); u[l] is 0 for the
+ * others.  For the lanes that do, the top six bits come from the planes, and a
+ * lane whose top six bits equal its threshold's (a tie) gets its low 26 bits
+ * from the TIE stream in ascending lane order.  Each u[l] of a comparing lane
+ * is a uniform 32-bit integer as far as u[l] < thr[l] is concerned: the low
+ * bits of a lane that is not tied cannot change that comparison.
+ */
+void oracle_word_uniforms(uint64_t seed, uint32_t w, uint32_t g, uint32_t h, const uint64_t thr[64],
+                          const int needs[64], uint32_t u[64]) {
+    uint32_t ties = 0;
+    for (uint32_t l = 0; l < 64; ++l) {
+        u[l] = 0;
+        if (!needs[l])
+            continue;
+        uint32_t top = oracle_sweep_top6(seed, w, g, h, l);
+        u[l] = top << 26;
+        if (top == (uint32_t)(thr[l] >> 26)) {
+            uint32_t x[4];
+            draw(seed, w, g, h, TAG_TIE | (ties >> 2), x);
+            u[l] |= x[ties & 3u] >> 6;
+            ++ties;
+        }
+    }
 }
 
 uint32_t oracle_resample_uniform(uint64_t seed, uint32_t step, uint32_t j) {
@@ -158,7 +191,11 @@ int oracle_delta_energy(int s, int h) { return 2 * s * h; }
  * integer thresholds t4 = ceil(2^32 exp(-4 beta)) and t8 = ceil(2^32
  * exp(-8 beta)) (both in [1, 2^32]); for an integer u32, u32 / 2^32 < p holds
  * exactly when u32 < ceil(2^32 p).  spins holds R replicas occupying slots
- * slot0 .. slot0 + R - 1 of the population (their slots select their uniforms).
+ * slot0 .. slot0 + R - 1 of the population (their slots select their
+ * uniforms).  The uniforms of a 64-replica group are drawn together
+ * (oracle_word_uniforms), so slot0 must be a multiple of 64 and spins must hold
+ * every replica of each group it touches (the last group may end early only
+ * where the population ends).
  */
 void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int theta,
                    uint64_t t4, uint64_t t8, int slot0) {
@@ -167,29 +204,46 @@ void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int the
     for (int sweep = 0; sweep < theta; ++sweep) {
         for (int colour = 0; colour < 2; ++colour) {
             uint32_t h = (uint32_t)(2 * (theta * (step - 1) + sweep) + colour);
-            for (int r = 0; r < R; ++r) {
-                int8_t *s = spins + (size_t)r * N;
-                int slot = slot0 + r; /* the replica's position in the population */
+            for (int r0 = 0; r0 < R; r0 += 64) {
+                int n_lanes = R - r0 < 64 ? R - r0 : 64;
+                uint32_t g = (uint32_t)((slot0 + r0) / 64);
                 for (int y = 0; y < L; ++y) {
                     for (int x = 0; x < L; ++x) {
                         if (((x + y) & 1) != colour)
                             continue;
-                        int here = s[y * L + x];
-                        int field = s[y * L + (x + 1) % L] + s[y * L + (x + L - 1) % L] +
-                                    s[((y + 1) % L) * L + x] + s[((y + L - 1) % L) * L + x];
-                        int dE = oracle_delta_energy(here, field);
-                        int flip;
-                        if (dE <= 0) {
-                            flip = 1;
-                        } else {
-                            uint32_t w = (uint32_t)(y * half + x / 2);
-                            uint64_t u = oracle_sweep_uniform(seed, w, (uint32_t)(slot / 64), h,
-                                                              (uint32_t)(slot % 64));
-                            uint64_t t = (dE == 4) ? t4 : t8;
-                            flip = u < t;
+                        int site = y * L + x;
+                        int dE[64];
+                        uint64_t thr[64];
+                        int needs[64];
+                        uint32_t u[64];
+                        for (int l = 0; l < 64; ++l) {
+                            dE[l] = 0;
+                            thr[l] = 0;
+                            needs[l] = 0;
+                            if (l >= n_lanes)
+                                continue;
+                            const int8_t *s = spins + (size_t)(r0 + l) * N;
+                            int field = s[y * L + (x + 1) % L] + s[y * L + (x + L - 1) % L] +
+                                        s[((y + 1) % L) * L + x] + s[((y + L - 1) % L) * L + x];
+                            dE[l] = oracle_delta_energy(s[site], field);
+                            if (dE[l] > 0) {
+                                thr[l] = (dE[l] == 4) ? t4 : t8;
+                                needs[l] = thr[l] < ((uint64_t)1 << 32);
+                            }
                         }
-                        if (flip)
-                            s[y * L + x] = (int8_t)(-here);
+                        oracle_word_uniforms(seed, (uint32_t)(y * half + x / 2), g, h, thr, needs, u);
+                        for (int l = 0; l < n_lanes; ++l) {
+                            int8_t *s = spins + (size_t)(r0 + l) * N;
+                            int flip;
+                            if (dE[l] <= 0)
+                                flip = 1;
+                            else if (!needs[l])
+                                flip = 1; /* threshold 2^32: every uniform is below it */
+                            else
+                                flip = (uint64_t)u[l] < thr[l];
+                            if (flip)
+                                s[site] = (int8_t)(-s[site]);
+                        }
                     }
                 }
             }

@@ -80,8 +80,11 @@ def lib():
         p_i32 = ctypes.POINTER(ctypes.c_int32)
         L.oracle_philox4x32_10.argtypes = [u32, u32, p_u32, p_u32]
         L.oracle_philox4x32_10.restype = None
-        L.oracle_sweep_uniform.argtypes = [u64, u32, u32, u32, u32]
-        L.oracle_sweep_uniform.restype = u32
+        L.oracle_sweep_top6.argtypes = [u64, u32, u32, u32, u32]
+        L.oracle_sweep_top6.restype = u32
+        L.oracle_word_uniforms.argtypes = [u64, u32, u32, u32, ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_int), p_u32]
+        L.oracle_word_uniforms.restype = None
         L.oracle_resample_uniform.argtypes = [u64, u32, u32]
         L.oracle_resample_uniform.restype = u32
         L.oracle_multinomial_uniform.argtypes = [u64, u32, u32]
@@ -113,8 +116,21 @@ def philox4x32_10(key: int, ctr) -> np.ndarray:
     return out
 
 
-def sweep_uniform(seed: int, w: int, g: int, h: int, lane: int) -> int:
-    return int(lib().oracle_sweep_uniform(seed, w, g, h, lane))
+def sweep_top6(seed: int, w: int, g: int, h: int, lane: int) -> int:
+    """Top six bits of lane `lane`'s Metropolis uniform in word (w, g, h)."""
+    return int(lib().oracle_sweep_top6(seed, w, g, h, lane))
+
+
+def word_uniforms(seed: int, w: int, g: int, h: int, thr, needs) -> np.ndarray:
+    """The 64 Metropolis uniforms of word (w, g, h) for per-lane thresholds thr
+    and the lanes that compare at all (needs); 0 where needs is false."""
+    t = np.ascontiguousarray(np.asarray(thr, dtype=np.uint64))
+    n = np.ascontiguousarray(np.asarray(needs, dtype=np.intc))
+    assert t.shape == (64,) and n.shape == (64,)
+    u = np.zeros(64, dtype=np.uint32)
+    lib().oracle_word_uniforms(seed, w, g, h, _ptr(t, ctypes.c_uint64), _ptr(n, ctypes.c_int),
+                               _ptr(u, ctypes.c_uint32))
+    return u
 
 
 def resample_uniform(seed: int, step: int, j: int) -> int:
@@ -149,9 +165,12 @@ def sweeps(seed: int, L: int, spins: np.ndarray, step: int, theta: int, t4: int,
            slot0: int = 0) -> None:
     """theta checkerboard Metropolis sweeps, in place, for step >= 1.
 
-    spins[k] is the replica in population slot slot0 + k.
+    spins[k] is the replica in population slot slot0 + k; a group's 64
+    uniforms are drawn together, so slot0 is a multiple of 64 and spins holds
+    whole groups (the last may be short only where the population ends).
     """
     assert spins.dtype == np.int8 and spins.flags.c_contiguous
+    assert slot0 % 64 == 0, "sweeps take whole 64-replica groups"
     R = spins.shape[0]
     if R and theta:
         lib().oracle_sweeps(seed, L, R, _ptr(spins, ctypes.c_int8), step, theta, t4, t8, slot0)

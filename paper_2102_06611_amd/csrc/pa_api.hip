@@ -789,7 +789,7 @@ pa_status pa_overlap(pa_ctx *ctx, double dbeta, double *alpha) {
     pa_batch *B = &ctx->b;
     if (!(dbeta >= 0) || !std::isfinite(dbeta)) return fail(B, PA_ERR_ARG, "dbeta must be finite and >= 0");
     PA_HIP(B, launch_hist_current(B->lc));
-    PA_HIP(B, launch_overlap(B->lc, 0, dbeta, 0.0, 0));
+    PA_HIP(B, launch_overlap(B->lc, 0, dbeta));
     RunState s;
     pa_status e = read_state(B, 0, &s);
     if (e) return e;
@@ -803,7 +803,7 @@ pa_status pa_adaptive_dbeta(pa_ctx *ctx, double alpha_target, double dbeta_max, 
     if (!(alpha_target > 0 && alpha_target < 1)) return fail(B, PA_ERR_ARG, "alpha_target must be in (0, 1)");
     if (!(dbeta_max > 0) || !std::isfinite(dbeta_max)) return fail(B, PA_ERR_ARG, "dbeta_max must be > 0");
     PA_HIP(B, launch_hist_current(B->lc));
-    PA_HIP(B, launch_overlap(B->lc, 0, dbeta_max, alpha_target, 1));
+    PA_HIP(B, launch_schedule(B->lc, 0, nullptr, 0.0, alpha_target, dbeta_max, 0, nullptr));
     RunState s;
     pa_status e = read_state(B, 0, &s);
     if (e) return e;

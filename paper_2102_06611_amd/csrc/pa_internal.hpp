@@ -44,7 +44,7 @@ hipError_t launch_reduce(const LaunchCtx &c);
 hipError_t launch_step(const LaunchCtx &c);
 hipError_t launch_resample(const LaunchCtx &c);
 hipError_t launch_hist_current(const LaunchCtx &c);
-hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta, double target, int mode);
+hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta);
 hipError_t launch_set_beta(const LaunchCtx &c, int r, int idx, double beta);
 hipError_t launch_unpack_group(const LaunchCtx &c, int r, int g, int N);
 hipError_t launch_pack_group(const LaunchCtx &c, int r, int g, int buf, int n_valid, int N);

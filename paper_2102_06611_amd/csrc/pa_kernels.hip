@@ -636,12 +636,42 @@ __device__ __forceinline__ uint64_t plane_pair(uint64_t &und, uint64_t eq1, uint
     return planes_step(und, eq1, T4, T8, p, x);
 }
 
-// Lane-local variant: the whole lazy comparison of one word in its own lane.  With
+// Ties after the planes: the lanes whose top six uniform bits equal their
+// threshold's take fresh low 26 bits, four per Philox call, in ascending lane
+// order (call q = kTagTie | k, output word k & 3 for the k-th tie).  One such
+// comparison decides a tie: u < T iff low26(u) < low26(T).
+constexpr uint32_t kPlanePairs = 3;            // Philox calls of bit planes: the top six bits
+constexpr uint32_t kTagTie = kTagSweep | 0x100u;
+constexpr uint32_t kLow26 = (1u << 26) - 1u;
+
+__device__ __forceinline__ void tie_one(uint64_t &und, uint64_t eq1, uint32_t L4, uint32_t L8,
+                                        uint32_t v, uint64_t &flip) {
+    if (und) {
+        const uint32_t lo = (uint32_t)und, hi = (uint32_t)(und >> 32);
+        const uint32_t j = lo ? (uint32_t)__builtin_ctz(lo) : 32u + (uint32_t)__builtin_ctz(hi);
+        const uint64_t bit = 1ull << j;
+        und &= und - 1ull;
+        const uint32_t t = (eq1 & bit) ? L4 : L8;
+        if ((v >> 6) < t) flip |= bit;
+    }
+}
+
+__device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t L4, uint32_t L8,
+                                         const U4 &x, uint64_t &flip) {
+    tie_one(und, eq1, L4, L8, x.x, flip);
+    tie_one(und, eq1, L4, L8, x.y, flip);
+    tie_one(und, eq1, L4, L8, x.z, flip);
+    tie_one(und, eq1, L4, L8, x.w, flip);
+}
+
+// Lane-local variant: the whole comparison of one word in its own lane.  With
 // a_k = s XOR n_k (antiparallel neighbours), A = sum a_k and dE = 8 - 4A:
 // A >= 2 (dE <= 0) always flips; A = 1 (dE = 4) and A = 0 (dE = 8) flip iff
-// u32 < t4 / t8.  u32 is compared bit plane by bit plane from the most
-// significant one, generating planes only while some lane is still tied with
-// its threshold; this equals the full 32-bit comparison.
+// u32 < t4 / t8.  The top six bits of u32 are compared bit plane by bit plane
+// from the most significant one, generating planes only while some lane is
+// still tied with its threshold; the lanes tied after six planes are decided
+// by one comparison of fresh low bits each.  This equals the full 32-bit
+// comparison.
 __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, uint64_t a3,
                                                     uint64_t a4, uint64_t valid, uint64_t t4,
                                                     uint64_t t8, bool all4, bool all8,
@@ -663,11 +693,16 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
     uint32_t p = 0;
-    for (; und != 0 && p < 16; ++p) {
+    for (; und != 0 && p < kPlanePairs; ++p) {
         const U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
         flip |= planes_step(und, eq1, T4, T8, p, x);
     }
-    *calls += p;
+    uint32_t q = 0;
+    for (; und != 0; ++q) {
+        const U4 x = philox(k0, k1, w, g, h, kTagTie | q);
+        tie_call(und, eq1, T4 & kLow26, T8 & kLow26, x, flip);
+    }
+    *calls += p + q;
     return flip;
 }
 
@@ -705,15 +740,14 @@ __device__ __forceinline__ WordPos word_pos(int idx, int colour, int L, int N, i
 // lattices live in LDS as gpb * N words for all theta sweeps (colour 0 then
 // colour 1; a site's index within its colour w = y L/2 + floor(x/2) and the
 // global half-sweep index h = 2 (theta (i-1) + sweep) + colour key its random
-// planes).  A half-sweep takes its words in batches of cpl per lane: every
-// word first gets up to kPhaseA Philox calls in its own lane; the words with
+// bits).  Variant 0 (lane-local) runs each word's whole comparison in one
+// lane.  Variant 1 (pooled) takes a half-sweep's words in batches of cpl per
+// lane: every word first gets its plane calls in its own lane; the words with
 // lanes still tied go to a per-wavefront list, which all 64 lanes then work
-// through one plane pair per round, so that the few long comparisons do not
-// hold up a whole wavefront.  Afterwards each replica's E = 2U - 2N (U
+// through one tie call per round.  Afterwards each replica's E = 2U - 2N (U
 // antiparallel bonds) and M are measured.  With init != 0 no sweep is done.
 constexpr int kMaxGroupsPerBlock = 8;
 
-constexpr uint32_t kPhaseA = 3;  // Philox calls per word before a word is listed
 
 template <int LAYOUT, int POOLED>
 __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map, int init,
@@ -782,7 +816,7 @@ __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map
                 continue;
             }
             for (int b0 = 0; b0 < words; b0 += cpl * nt) {
-                // phase A: each lane takes cpl words and spends up to kPhaseA
+                // phase A: each lane takes cpl words and spends up to kPlanePairs
                 // Philox calls on each; still undecided words go to the list
                 int cnt = 0;
                 for (int k = 0; k < cpl; ++k) {
@@ -802,7 +836,7 @@ __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map
                         c.eq1 &= valid;
                         und = (c.eq1 | c.eq0) & valid;
 #pragma unroll
-                        for (uint32_t p = 0; p < kPhaseA; ++p) {
+                        for (uint32_t p = 0; p < kPlanePairs; ++p) {
                             if (und) {
                                 const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagSweep | p);
                                 flip |= plane_pair(und, c.eq1, T4, T8, p, x);
@@ -820,10 +854,10 @@ __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map
                     }
                     cnt += __popcll(m);
                 }
-                // phase B: one plane pair per round for every listed word, all
+                // phase B: one tie call per round for every listed word, all
                 // lanes of the wavefront working on the list
                 int cur = 0;
-                for (uint32_t p = kPhaseA; cnt > 0 && p < 16; ++p) {
+                for (uint32_t q = 0; cnt > 0; ++q) {
                     int next = 0;
                     for (int base = 0; base < cnt; base += kLanes) {
                         const int e = base + lane;
@@ -840,8 +874,9 @@ __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map
                             const uint64_t s0 = lat[w.site];
                             const WordClass c = classify(s0 ^ lat[w.r], s0 ^ lat[w.l], s0 ^ lat[w.u],
                                                          s0 ^ lat[w.d]);
-                            const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagSweep | p);
-                            const uint64_t acc = plane_pair(und, c.eq1 & und, T4, T8, p, x);
+                            const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagTie | q);
+                            uint64_t acc = 0;
+                            tie_call(und, c.eq1, T4 & kLow26, T8 & kLow26, x, acc);
                             ++calls;
                             if (acc) lat[w.site] = s0 ^ acc;
                         }
@@ -857,7 +892,6 @@ __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map
                     cur ^= 1;
                     cnt = next;
                 }
-                // lanes still tied after 32 planes have u32 == T: rejected
             }
             __syncthreads();
         }
@@ -1110,31 +1144,14 @@ __global__ void k_set_beta(const RunDesc *runs, int r, int idx, double beta) {
 
 // ------------------------------------------------------------------ overlap / adaptive step
 
-// mode 0: alpha at dbeta; mode 1: bisection for alpha(dbeta) = target on (0, dbeta].
-__global__ void __launch_bounds__(256) k_overlap(const RunDesc *runs, int r, double dbeta,
-                                                 double target, int mode) {
+// alpha(dbeta) of the current population (one block).
+__global__ void __launch_bounds__(256) k_overlap(const RunDesc *runs, int r, double dbeta) {
     const RunDesc &rd = runs[r];
     RunState *st = rd.st;
     __shared__ double shd[32];
     const int kmin = st->kmin, nlev = st->kmax - st->kmin + 1, R = st->R_cur;
-    if (mode == 0) {
-        double a = overlap_block(rd, kmin, nlev, R, dbeta, shd);
-        if (threadIdx.x == 0) st->alpha_out = a;
-        return;
-    }
-    double hi = dbeta;
-    double ahi = overlap_block(rd, kmin, nlev, R, hi, shd);
-    if (ahi >= target) {
-        if (threadIdx.x == 0) { st->dbeta_out = hi; st->alpha_out = ahi; }
-        return;
-    }
-    double lo = 0.0, alo = 1.0;
-    for (int it = 0; it < 60; ++it) {
-        double mid = 0.5 * (lo + hi);
-        double am = overlap_block(rd, kmin, nlev, R, mid, shd);
-        if (am >= target) { lo = mid; alo = am; } else { hi = mid; }
-    }
-    if (threadIdx.x == 0) { st->dbeta_out = lo; st->alpha_out = alo; }
+    const double a = overlap_block(rd, kmin, nlev, R, dbeta, shd);
+    if (threadIdx.x == 0) st->alpha_out = a;
 }
 
 // ------------------------------------------------------------------ workspace clear
@@ -1249,8 +1266,8 @@ hipError_t launch_hist_current(const LaunchCtx &c) {
     return hipSuccess;
 }
 
-hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta, double target, int mode) {
-    PA_LAUNCH(k_overlap, dim3(1), dim3(256), 0, c.stream, c.runs, r, dbeta, target, mode);
+hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta) {
+    PA_LAUNCH(k_overlap, dim3(1), dim3(256), 0, c.stream, c.runs, r, dbeta);
     return hipSuccess;
 }
 

@@ -47,31 +47,82 @@ def test_philox_matches_rocrand(rocrand_ref):
         assert list(po.philox4x32_10(seed, ctr)) == r, (seed, ctr)
 
 
-def test_sweep_uniform_is_built_from_bit_planes():
-    # lane l's uniform: bit (31 - b) is bit l of plane b; planes 2p, 2p+1 come
-    # from Philox call p with counter (w, g, h, 0x10000000 | p)
+def test_sweep_uniform_top_bits_and_ties_follow_the_stream_map():
+    # lane l's top six bits: bit (5 - b) is bit l of plane b; planes 2p, 2p+1
+    # come from call (w, g, h, 0x10000000 | p).  A lane whose top six bits equal
+    # its threshold's takes its low 26 bits from word k & 3 of call (w, g, h,
+    # 0x10000100 | k >> 2), k = its rank among the tied lanes.
     seed, w, g, h = 99, 5, 3, 17
     planes = []
-    for p in range(16):
+    for p in range(3):
         x = po.philox4x32_10(seed, [w, g, h, 0x10000000 | p]).astype(np.uint64)
         planes += [int(x[0] | (x[1] << np.uint64(32))), int(x[2] | (x[3] << np.uint64(32)))]
+    top = [sum(((planes[b] >> lane) & 1) << (5 - b) for b in range(6)) for lane in range(64)]
     for lane in (0, 1, 31, 32, 63):
-        u = sum(((planes[b] >> lane) & 1) << (31 - b) for b in range(32))
-        assert po.sweep_uniform(seed, w, g, h, lane) == u
+        assert po.sweep_top6(seed, w, g, h, lane) == top[lane]
+    # thresholds that tie every other lane, skip lane 7 entirely
+    thr = [((top[l] if l % 2 == 0 else top[l] ^ 1) << 26) | 0x1234567 for l in range(64)]
+    needs = [l != 7 for l in range(64)]
+    u = po.word_uniforms(seed, w, g, h, thr, needs)
+    tied = [l for l in range(64) if needs[l] and l % 2 == 0]
+    for k, l in enumerate(tied):
+        x = po.philox4x32_10(seed, [w, g, h, 0x10000100 | (k >> 2)])
+        assert int(u[l]) == (top[l] << 26) | (int(x[k & 3]) >> 6)
+    for l in range(64):
+        if not needs[l]:
+            assert u[l] == 0
+        elif l % 2:
+            assert int(u[l]) == top[l] << 26
+
+
+def _acceptance(seed, thr_of_lane, n_words):
+    """Fraction of u < thr over n_words words (all lanes comparing)."""
+    acc = np.zeros(64)
+    for w in range(n_words):
+        thr = [thr_of_lane(l) for l in range(64)]
+        u = po.word_uniforms(seed, w, 1, 2, thr, [True] * 64).astype(np.uint64)
+        acc += u < np.asarray(thr, dtype=np.uint64)
+    return acc / n_words
+
+
+@pytest.mark.parametrize("T", [1, 0x02000000, 0x03FFFFFF, 0x7C000001, 0x8000_0000, 0xB504F334,
+                               0xFFFFFFFF])
+def test_comparison_with_tied_top_bits_is_exact_bernoulli(T):
+    # u < T must hold with probability T / 2^32 whether it is decided by the
+    # top six bits or by a tie's 26 fresh bits (thresholds with small, zero and
+    # full low parts; one per lane class)
+    n = 400
+    p = T / 2.0 ** 32
+    frac = _acceptance(31, lambda l: T, n).mean()
+    sigma = np.sqrt(p * (1 - p) / (64 * n))
+    assert abs(frac - p) <= 5 * sigma + 1e-12
+
+
+def test_comparison_with_mixed_thresholds_per_lane():
+    # lanes of one word comparing with two thresholds (the dE = 4 and dE = 8
+    # classes) keep their own acceptance probabilities while sharing tie draws
+    t4, t8 = 0x9A3C2B11, 0x07A5D003
+    n = 600
+    frac = _acceptance(7, lambda l: t4 if l % 3 else t8, n)
+    for lanes, t in (([l for l in range(64) if l % 3], t4), ([l for l in range(64) if l % 3 == 0], t8)):
+        p = t / 2.0 ** 32
+        f = frac[lanes].mean()
+        assert abs(f - p) <= 5 * np.sqrt(p * (1 - p) / (len(lanes) * n))
 
 
 def test_stream_uniformity():
-    # 64-lane sweep uniforms and resampling uniforms are flat on [0, 2^32)
-    us = np.array([po.sweep_uniform(5, w, 0, 1, lane) for w in range(64) for lane in range(64)],
-                  dtype=np.float64) / 2 ** 32
+    # top six bits of the sweep uniforms, resampling and multinomial uniforms
+    # are flat
+    ts = np.array([po.sweep_top6(5, w, 0, 1, lane) for w in range(64) for lane in range(64)],
+                  dtype=np.float64) / 64
     rs = np.array([po.resample_uniform(5, 3, j) for j in range(4096)], dtype=np.float64) / 2 ** 32
     ms = np.array([po.multinomial_uniform(5, 3, d) for d in range(4096)], dtype=np.float64) / 2 ** 64
-    for x in (us, rs, ms):
+    for x in (ts, rs, ms):
         hist, _ = np.histogram(x, bins=16, range=(0, 1))
         expected = len(x) / 16
         chi2 = ((hist - expected) ** 2 / expected).sum()
         assert chi2 < 50  # 15 dof: p ~ 1e-5
-        assert abs(x.mean() - 0.5) < 5 * np.sqrt(1 / 12 / len(x))
+        assert abs(x.mean() + (1 / 128 if x is ts else 0) - 0.5) < 5 * np.sqrt(1 / 12 / len(x))
 
 
 def test_init_spins_are_fair_and_seeded():
