@@ -599,6 +599,28 @@ __device__ __forceinline__ WordClass classify(uint64_t a1, uint64_t a2, uint64_t
     return WordClass{ge2, any & ~ge2, ~any};
 }
 
+// The same classes per 32-bit half with three-input operations: with m =
+// maj(a1, a2, a3) and o = a1 | a2 | a3, A >= 2 is m | (a4 & o) and A = 1 is
+// (o | a4) & ~(A >= 2).
+struct WordClass2 {
+    uint64_t ge2, eq1;
+};
+__device__ __forceinline__ uint32_t ge2_half(uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                                             uint32_t *eq1) {
+    const uint32_t m = __builtin_amdgcn_bitop3_b32(a1, a2, a3, 0xE8);   // maj
+    const uint32_t o = __builtin_amdgcn_bitop3_b32(a1, a2, a3, 0xFE);   // or
+    const uint32_t g = __builtin_amdgcn_bitop3_b32(m, a4, o, 0xF8);     // m | (a4 & o)
+    *eq1 = __builtin_amdgcn_bitop3_b32(o, a4, g, 0x54);                 // (o | a4) & ~g
+    return g;
+}
+__device__ __forceinline__ WordClass2 classes(uint64_t a1, uint64_t a2, uint64_t a3, uint64_t a4) {
+    uint32_t e_lo, e_hi;
+    const uint32_t g_lo = ge2_half((uint32_t)a1, (uint32_t)a2, (uint32_t)a3, (uint32_t)a4, &e_lo);
+    const uint32_t g_hi = ge2_half((uint32_t)(a1 >> 32), (uint32_t)(a2 >> 32), (uint32_t)(a3 >> 32),
+                                   (uint32_t)(a4 >> 32), &e_hi);
+    return WordClass2{((uint64_t)g_hi << 32) | g_lo, ((uint64_t)e_hi << 32) | e_lo};
+}
+
 // Two bit planes (one Philox call) of the lazy comparison u32 < T, from the
 // most significant plane down: a lane still tied with its threshold (und) is
 // decided by the first plane where its bit differs from T's bit (T4's for the
@@ -646,14 +668,10 @@ constexpr uint32_t kLow26 = (1u << 26) - 1u;
 
 __device__ __forceinline__ void tie_one(uint64_t &und, uint64_t eq1, uint32_t L4, uint32_t L8,
                                         uint32_t v, uint64_t &flip) {
-    if (und) {
-        const uint32_t lo = (uint32_t)und, hi = (uint32_t)(und >> 32);
-        const uint32_t j = lo ? (uint32_t)__builtin_ctz(lo) : 32u + (uint32_t)__builtin_ctz(hi);
-        const uint64_t bit = 1ull << j;
-        und &= und - 1ull;
-        const uint32_t t = (eq1 & bit) ? L4 : L8;
-        if ((v >> 6) < t) flip |= bit;
-    }
+    const uint64_t bit = und & (0ull - und);  // lowest tied lane; 0 when none is left
+    und ^= bit;
+    const uint32_t t = (eq1 & bit) ? L4 : L8;
+    flip |= ((v >> 6) < t) ? bit : 0ull;
 }
 
 __device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t L4, uint32_t L8,
@@ -677,18 +695,15 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
                                                     uint64_t t8, bool all4, bool all8,
                                                     uint32_t k0, uint32_t k1, uint32_t w,
                                                     uint32_t g, uint32_t h, uint32_t *calls) {
-    const uint64_t x12 = a1 ^ a2, y12 = a1 & a2, x34 = a3 ^ a4, y34 = a3 & a4;
-    const uint64_t ge2 = y12 | y34 | (x12 & x34);
-    const uint64_t any = x12 | y12 | x34 | y34;
-    uint64_t eq1 = any & ~ge2;
-    uint64_t eq0 = ~any;
-    uint64_t flip = ge2;
-    if (all4) { flip |= eq1; eq1 = 0; }
-    if (all8) { flip |= eq0; eq0 = 0; }
-    flip &= valid;
-    eq1 &= valid;
-    eq0 &= valid;
-    uint64_t und = eq1 | eq0;
+    const WordClass2 c = classes(a1, a2, a3, a4);
+    const uint64_t eq1 = c.eq1;
+    uint64_t flip = c.ge2 & valid;
+    uint64_t und = valid & ~c.ge2;
+    if (all4 || all8) {  // beta <= 0: a threshold of 2^32 accepts its whole class
+        const uint64_t e1 = und & eq1, e0 = und & ~eq1;
+        if (all4) { flip |= e1; und &= ~e1; }
+        if (all8) { flip |= e0; und &= ~e0; }
+    }
     // the thresholds are the same for every lane: keep their bits in scalar registers
     const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
@@ -734,6 +749,37 @@ __device__ __forceinline__ WordPos word_pos(int idx, int colour, int L, int N, i
     w.u = ((y == 0) ? base + N - L : row - L) + x;
     w.d = ((y == L - 1) ? base : row + L) + x;
     return w;
+}
+
+// Incremental walk over the words idx, idx + nt, ... of one colour: half-column
+// xh = idx mod L/2 and global row r = idx div L/2 = gl L + y, kept as (xh, y,
+// gl, row = r L) and advanced by nt words with one carry each, so that no
+// division is needed per word.
+struct WordWalk {
+    int xh, y, gl, row;
+};
+struct WalkStep {
+    int half, L, dxh, dy, dgl, drow;  // nt = (dgl L + dy) half + dxh, drow = (dgl L + dy) L
+};
+__device__ __forceinline__ WalkStep walk_step(int nt, int half, int L) {
+    const int dr = nt / half;
+    return WalkStep{half, L, nt - dr * half, dr % L, dr / L, dr * L};
+}
+__device__ __forceinline__ WordWalk walk_start(int idx, int half, int L) {
+    const int r = idx / half;
+    return WordWalk{idx - r * half, r % L, r / L, r * L};
+}
+__device__ __forceinline__ void walk_advance(WordWalk &w, const WalkStep &s) {
+    w.xh += s.dxh;
+    const int c = w.xh >= s.half ? 1 : 0;
+    w.xh -= c ? s.half : 0;
+    w.row += s.drow + (c ? s.L : 0);
+    w.y += s.dy + c;
+    w.gl += s.dgl;
+    if (w.y >= s.L) {
+        w.y -= s.L;
+        w.gl += 1;
+    }
 }
 
 // One block per (run, gpb consecutive groups): the groups' L x L x 64
@@ -788,6 +834,8 @@ __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
     const float inv_half = 1.0f / (float)half, inv_L = 1.0f / (float)L;
     const int words = ng * (N >> 1);  // sites of one colour, all groups of the block
+    const uint64_t last_valid = lane_mask(Rn - (g0 + ng - 1) * kLanes);
+    const WalkStep step = walk_step(nt, half, L);
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     // per-wavefront lists of undecided words (two, used alternately): word
     // index and the mask of still undecided lanes
@@ -801,16 +849,24 @@ __global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map
         for (int colour = 0; colour < 2; ++colour) {
             const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
             if (!POOLED) {
-                // lane-local: each word's comparison runs to the end in its lane
+                // lane-local: each word's comparison runs to the end in its lane;
+                // the thread walks the words tid, tid + nt, ... incrementally
+                WordWalk wk = walk_start(tid, half, L);
                 for (int idx = tid; idx < words; idx += nt) {
-                    const WordPos w = word_pos(idx, colour, L, N, half, inv_half, inv_L);
-                    const int g = g0 + w.gl;
-                    const uint64_t s0 = lat[w.site];
-                    const uint64_t f = metropolis_word(s0 ^ lat[w.r], s0 ^ lat[w.l], s0 ^ lat[w.u],
-                                                       s0 ^ lat[w.d], lane_mask(Rn - g * kLanes), t4,
-                                                       t8, all4, all8, k0, k1, (uint32_t)w.wi,
-                                                       (uint32_t)g, h, &calls);
-                    lat[w.site] = s0 ^ f;
+                    const int x = 2 * wk.xh + ((colour + wk.y) & 1);
+                    const int site = wk.row + x;
+                    const int rgt = (x == L - 1) ? wk.row : site + 1;
+                    const int lft = (x == 0) ? site + L - 1 : site - 1;
+                    const int up = (wk.y == 0) ? site + N - L : site - L;
+                    const int dn = (wk.y == L - 1) ? site + L - N : site + L;
+                    const uint64_t s0 = lat[site];
+                    const uint64_t valid = wk.gl == ng - 1 ? last_valid : ~0ull;
+                    const uint64_t f = metropolis_word(s0 ^ lat[rgt], s0 ^ lat[lft], s0 ^ lat[up],
+                                                       s0 ^ lat[dn], valid, t4, t8, all4, all8, k0,
+                                                       k1, (uint32_t)(wk.y * half + wk.xh),
+                                                       (uint32_t)(g0 + wk.gl), h, &calls);
+                    lat[site] = s0 ^ f;
+                    walk_advance(wk, step);
                 }
                 __syncthreads();
                 continue;
