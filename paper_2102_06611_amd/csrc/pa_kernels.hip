@@ -504,16 +504,77 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
 
 // ------------------------------------------------------------------ copy / compaction
 
+// Bit networks of the multispin gather (compress and expand of a 64-bit word
+// under a selector, Hacker's Delight Sec. 7-4 / 7-5): six stages that move
+// bits by 1, 2, 4, 8, 16 and 32 places.  The per-stage move masks depend only
+// on the selector, so one child group computes them once (uniform, scalar
+// registers) and applies them to every site word.
+struct Network {
+    uint64_t mv[6];
+    uint64_t m;  // the selector
+};
+__device__ __forceinline__ Network network_masks(uint64_t m) {
+    Network n;
+    n.m = m;
+    uint64_t mk = ~m << 1;  // marks the zeros of m to the right of each bit
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        uint64_t mp = mk ^ (mk << 1);  // parallel suffix (prefix xor from the right)
+        mp ^= mp << 2;
+        mp ^= mp << 4;
+        mp ^= mp << 8;
+        mp ^= mp << 16;
+        mp ^= mp << 32;
+        const uint64_t mv = mp & m;
+        m = (m ^ mv) | (mv >> (1 << i));
+        n.mv[i] = mv;
+        mk &= ~mp;
+    }
+    return n;
+}
+// Selected bits of x, moved to the low end in order (bits of x outside the
+// selector are dropped).
+__device__ __forceinline__ uint64_t net_compress(uint64_t x, const Network &n) {
+    x &= n.m;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        if (n.mv[i]) {  // uniform
+            const uint64_t t = x & n.mv[i];
+            x = (x ^ t) | (t >> (1 << i));
+        }
+    }
+    return x;
+}
+// The low bits of x, spread in order over the selector's positions.
+__device__ __forceinline__ uint64_t net_expand(uint64_t x, const Network &n) {
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        if (n.mv[i]) {  // uniform
+            const uint64_t t = x << (1 << i);
+            x = (x & ~n.mv[i]) | (t & n.mv[i]);
+        }
+    }
+    return x & n.m;
+}
+
 // Child c of destination group gd takes the spins and family label of parent
 // p(c) = the last j with off[j] <= c; parents stay in ascending order, so the
 // copies of one parent are adjacent (tree order).  Every wavefront finds the
 // parents of the group's 64 children (lane = child) and then:
-//  - multispin: lane = site; the destination word is assembled bit by bit from
-//    the parents' words, the parent index broadcast with readlane (uniform),
-//    so each bit costs one extract and one shift-or;
-//  - int8: lane = child; one byte per lane per site row, contiguous in both
-//    the parents' and the children's rows.
+//  - multispin: the child word of a site is a monotone bit map of at most a
+//    few parent words.  Per parent group pg the surviving parents that feed
+//    this child group form a selector P_pg; compressing each parent word by
+//    P_pg and concatenating gives the distinct parents' bits S in order;
+//    expanding S onto the run heads D (children whose parent differs from
+//    the previous child's) and OR-filling each run of copies gives the child
+//    word.  Lane = four consecutive sites.
+//  - int8: the parents' rows of kGatherSites sites at a time are staged in LDS
+//    (16-byte loads); thread = one dword (four children) of every 16th row.
+constexpr int kGatherPg = 4;      // int8: parent groups staged per pass
+constexpr int kGatherSites = 64;  // int8: site rows per pass
+
 __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map) {
+    __shared__ uint4 stage[kGatherPg * kGatherSites * 4];  // int8: groups x rows x 64 bytes
     int gd;
     const RunDesc &rd = runs[map_block(map, xcd_swizzle(blockIdx.x, gridDim.x), &gd)];
     RunState *st = rd.st;
@@ -533,53 +594,106 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
         p = lo;
     }
     if (wave == 0 && c < rd.C) rd.fam[nb][c] = p >= 0 ? rd.fam[cur][p] : 0;
-    const int n_valid = min(kLanes, Rn - gd * kLanes);
+    const int nv = __builtin_amdgcn_readfirstlane(min(kLanes, Rn - gd * kLanes));
+    const int g_first = __builtin_amdgcn_readlane(p, 0) >> 6;
+    const int g_last = __builtin_amdgcn_readlane(p, nv - 1) >> 6;
     if (rd.layout == PA_LAYOUT_MSC64) {
-        // lane = 4 consecutive sites; the 64 children are unrolled so that the
-        // parent index (readlane) and the bit positions are scalar operands
         const uint64_t *src = rd.ms[cur];
         uint64_t *dst = rd.ms[nb] + (size_t)gd * N;
-        const int nv = __builtin_amdgcn_readfirstlane(n_valid);
-        // parent groups of the children, first and last (the map is monotone)
-        const int g_first = __builtin_amdgcn_readlane(p, 0) >> 6;
-        const int g_last = __builtin_amdgcn_readlane(p, nv - 1) >> 6;
+        const int p_prev = __shfl_up(p, 1, 64);
+        const bool live = lane < nv;
+        const uint64_t D = __ballot(live && (lane == 0 || p != p_prev));  // run heads
+        const uint64_t F = __ballot(live && lane > 0 && p == p_prev);     // copies after a head
+        const Network ND = network_masks(D);
+        const int c_lo = gd * kLanes, c_hi = gd * kLanes + nv;
         for (int site0 = wave * 256; site0 < N; site0 += nw * 256) {
             const int sb = site0 + 4 * lane;
             const bool in = sb < N;  // N = L^2 is a multiple of 4
-            uint32_t lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+            uint64_t S[4] = {0, 0, 0, 0};
+            int shift = 0;
             for (int pg = g_first; pg <= g_last; ++pg) {
-                uint64_t w[4] = {0, 0, 0, 0};
+                // parents j = 64 pg + k of this group that have a copy in [c_lo, c_hi)
+                const int j = pg * kLanes + lane;
+                bool feeds = false;
+                if (j < Rp) {
+                    const int o0 = rd.off[j], o1 = rd.off[j + 1];
+                    feeds = o1 > o0 && o0 < c_hi && o1 > c_lo;
+                }
+                const uint64_t P = __ballot(feeds);
+                if (!P) continue;
+                const Network NP = network_masks(P);
                 if (in) {
                     const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(src + (size_t)pg * N + sb);
                     const ulonglong2 v0 = q[0], v1 = q[1];
-                    w[0] = v0.x; w[1] = v0.y; w[2] = v1.x; w[3] = v1.y;
+                    S[0] |= net_compress(v0.x, NP) << shift;
+                    S[1] |= net_compress(v0.y, NP) << shift;
+                    S[2] |= net_compress(v1.x, NP) << shift;
+                    S[3] |= net_compress(v1.y, NP) << shift;
                 }
-#pragma unroll
-                for (int l = 0; l < kLanes; ++l) {
-                    const int pl = __builtin_amdgcn_readlane(p, l);
-                    if (l < nv && (pl >> 6) == pg) {
-                        const uint32_t sh = (uint32_t)pl & 63u;
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint32_t bit = (uint32_t)(w[k] >> sh) & 1u;
-                            if (l < 32) lo[k] |= bit << l; else hi[k] |= bit << (l - 32);
-                        }
-                    }
-                }
+                shift += __popcll(P);
             }
             if (in) {
-                uint4 *q = reinterpret_cast<uint4 *>(dst + sb);
-                q[0] = uint4{lo[0], hi[0], lo[1], hi[1]};
-                q[1] = uint4{lo[2], hi[2], lo[3], hi[3]};
+                uint64_t o[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    uint64_t x = net_expand(S[k], ND);
+                    uint64_t Fk = F;
+                    for (int sh = 1; Fk; sh <<= 1) {  // OR-fill runs of copies (uniform)
+                        x |= (x << sh) & Fk;
+                        Fk &= Fk << sh;
+                    }
+                    o[k] = x;
+                }
+                ulonglong2 *q = reinterpret_cast<ulonglong2 *>(dst + sb);
+                q[0] = ulonglong2{o[0], o[1]};
+                q[1] = ulonglong2{o[2], o[3]};
             }
         }
     } else {
-        const int8_t *src = rd.s8[cur];
-        int8_t *dst = rd.s8[nb] + (size_t)gd * N * kLanes;
-        const size_t poff = p >= 0 ? (size_t)(p >> 6) * N * kLanes + (p & 63) : 0;
-        for (int site = wave; site < N; site += nw) {
-            const int8_t v = p >= 0 ? src[poff + (size_t)site * kLanes] : (int8_t)-1;
-            dst[(size_t)site * kLanes + lane] = v;
+        // thread -> dword k (children 4k .. 4k + 3) of site rows sl, sl + 16, ...
+        // of a chunk of kGatherSites rows
+        const uint4 *src = reinterpret_cast<const uint4 *>(rd.s8[cur]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(rd.s8[nb] + (size_t)gd * N * kLanes);
+        const int k = threadIdx.x & 15, sl = threadIdx.x >> 4;
+        int pc[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) pc[m] = __shfl(p, 4 * k + m, 64);
+        const uint8_t *st8 = reinterpret_cast<const uint8_t *>(stage);
+        for (int s0 = 0; s0 < N; s0 += kGatherSites) {
+            uint32_t out[kGatherSites / 16];
+#pragma unroll
+            for (int r = 0; r < kGatherSites / 16; ++r) {
+                out[r] = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (pc[m] < 0) out[r] |= 0xFFu << (8 * m);  // past the population: spin -1
+            }
+            for (int gb = g_first; gb <= g_last; gb += kGatherPg) {
+                const int ngb = min(kGatherPg, g_last - gb + 1);
+                __syncthreads();  // the previous pass's readers are done
+                // ngb groups x kGatherSites rows x 4 uint4, spread over the block
+                for (int e = threadIdx.x; e < ngb * kGatherSites * 4; e += blockDim.x) {
+                    const int b = e / (kGatherSites * 4), r = e - b * (kGatherSites * 4);
+                    const int srow = s0 + (r >> 2);
+                    if (srow < N) stage[e] = src[((size_t)(gb + b) * N + srow) * 4 + (r & 3)];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int rel = (pc[m] >> 6) - gb;
+                    if (pc[m] >= 0 && rel >= 0 && rel < ngb) {
+                        const uint8_t *row = st8 + rel * (kGatherSites * 64) + (pc[m] & 63);
+#pragma unroll
+                        for (int r = 0; r < kGatherSites / 16; ++r)
+                            out[r] |= (uint32_t)row[(sl + 16 * r) * 64] << (8 * m);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kGatherSites / 16; ++r) {
+                const int site = s0 + sl + 16 * r;
+                if (site < N) dst[(size_t)site * 16 + k] = out[r];
+            }
         }
     }
 }
@@ -796,7 +910,7 @@ constexpr int kMaxGroupsPerBlock = 8;
 
 
 template <int LAYOUT, int POOLED>
-__global__ void __launch_bounds__(1024) k_sweep(const RunDesc *runs, WorkMap map, int init,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_sweep(const RunDesc *runs, WorkMap map, int init,
                                                 int gpb, int cpl) {
     extern __shared__ uint64_t lat[];
     __shared__ int32_t red_u[kMaxGroupsPerBlock * kLanes], red_up[kMaxGroupsPerBlock * kLanes];
@@ -1045,7 +1159,7 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     }
     // exclusive max-scan of last_start over threads gives the run start entering each thread
     int x = last_start;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const int y = __shfl_up(x, o, 64);
