@@ -735,41 +735,70 @@ __device__ __forceinline__ WordClass2 classes(uint64_t a1, uint64_t a2, uint64_t
     return WordClass2{((uint64_t)g_hi << 32) | g_lo, ((uint64_t)e_hi << 32) | e_lo};
 }
 
-// Two bit planes (one Philox call) of the lazy comparison u32 < T, from the
-// most significant plane down: a lane still tied with its threshold (und) is
-// decided by the first plane where its bit differs from T's bit (T4's for the
-// dE = 4 lanes, T8's for the dE = 8 lanes); it is accepted when the plane bit
-// is 0 and T's is 1.  Returns the newly accepted lanes and updates und.  Per
-// 32-bit half and plane: t = T's bit per lane, accepted = und & t & ~plane,
-// und &= ~(t ^ plane) -- three v_bitop3 and one OR.  On the lanes still tied
-// the dE = 8 lanes are exactly those not in eq1, so t = eq1 ? T4-bit : T8-bit
-// there; elsewhere t does not matter.
-__device__ __forceinline__ uint32_t plane_bits(uint32_t &und, uint32_t eq1, uint32_t m4,
-                                               uint32_t m8, uint32_t pl) {
-    const uint32_t t = __builtin_amdgcn_bitop3_b32(eq1, m4, m8, 0xCA);    // eq1 ? m4 : m8
-    const uint32_t acc = __builtin_amdgcn_bitop3_b32(und, t, pl, 0x40);  // und & t & ~pl
-    und = __builtin_amdgcn_bitop3_b32(und, t, pl, 0x90);                 // und & ~(t ^ pl)
-    return acc;
+// One bit plane of the lazy comparison u32 < T, from the most significant
+// plane down, on one 32-bit half of a word: a lane still tied with its
+// threshold (und) is decided by the first plane where its bit differs from
+// T's bit (T4's for the dE = 4 lanes, T8's for the dE = 8 lanes; on the lanes
+// still tied the dE = 8 lanes are those not in eq1); it is accepted (flip) when
+// the plane bit is 0 and T's is 1.  The threshold bits b4, b8 of a plane are
+// the same for every lane, so each of their four combinations has its own
+// three-input form: t = 0 only rejects (und &= ~pl), t = 1 only accepts
+// (flip |= und & ~pl, und &= pl), and t = eq1 or ~eq1 does both.
+template <int B4, int B8>
+__device__ __forceinline__ void plane_half(uint32_t &und, uint32_t &flip, uint32_t eq1, uint32_t pl) {
+    if (!B4 && !B8) {  // t = 0
+        und = __builtin_amdgcn_bitop3_b32(und, pl, pl, 0x30);  // und & ~pl
+    } else if (B4 && B8) {  // t = 1
+        flip = __builtin_amdgcn_bitop3_b32(flip, und, pl, 0xF4);  // flip | (und & ~pl)
+        und &= pl;
+    } else if (B4) {  // t = eq1
+        const uint32_t acc = __builtin_amdgcn_bitop3_b32(und, eq1, pl, 0x40);  // und & eq1 & ~pl
+        und = __builtin_amdgcn_bitop3_b32(und, eq1, pl, 0x90);                 // und & ~(eq1 ^ pl)
+        flip |= acc;
+    } else {  // t = ~eq1
+        const uint32_t acc = __builtin_amdgcn_bitop3_b32(und, eq1, pl, 0x10);  // und & ~eq1 & ~pl
+        und = __builtin_amdgcn_bitop3_b32(und, eq1, pl, 0x60);                 // und & (eq1 ^ pl)
+        flip |= acc;
+    }
 }
 
-__device__ __forceinline__ uint64_t planes_step(uint64_t &und, uint64_t eq1, uint32_t T4,
-                                                uint32_t T8, uint32_t p, const U4 &x) {
+// Planes 2p and 2p + 1 (one Philox call x: plane 2p = x.x | x.y << 32, plane
+// 2p + 1 = x.z | x.w << 32) on a word's four 32-bit halves; one branch per
+// call picks the straight-line form for the four threshold bits.
+struct Lanes {
+    uint32_t ul, uh, fl, fh;  // undecided and accepted lanes, low and high halves
+};
+template <int C>
+__device__ __forceinline__ void plane_pair_case(Lanes &s, uint32_t el, uint32_t eh, const U4 &x) {
+    constexpr int A4 = (C >> 3) & 1, A8 = (C >> 2) & 1, B4 = (C >> 1) & 1, B8 = C & 1;
+    plane_half<A4, A8>(s.ul, s.fl, el, x.x);
+    plane_half<A4, A8>(s.uh, s.fh, eh, x.y);
+    plane_half<B4, B8>(s.ul, s.fl, el, x.z);
+    plane_half<B4, B8>(s.uh, s.fh, eh, x.w);
+}
+__device__ __forceinline__ void plane_pair(Lanes &s, uint32_t el, uint32_t eh, uint32_t T4,
+                                           uint32_t T8, uint32_t p, const U4 &x) {
     const uint32_t sa = 31u - 2u * p, sb = 30u - 2u * p;
-    const uint32_t m4a = 0u - ((T4 >> sa) & 1u), m8a = 0u - ((T8 >> sa) & 1u);
-    const uint32_t m4b = 0u - ((T4 >> sb) & 1u), m8b = 0u - ((T8 >> sb) & 1u);
-    uint32_t ul = (uint32_t)und, uh = (uint32_t)(und >> 32);
-    const uint32_t el = (uint32_t)eq1, eh = (uint32_t)(eq1 >> 32);
-    uint32_t al = plane_bits(ul, el, m4a, m8a, x.x);
-    uint32_t ah = plane_bits(uh, eh, m4a, m8a, x.y);
-    al |= plane_bits(ul, el, m4b, m8b, x.z);
-    ah |= plane_bits(uh, eh, m4b, m8b, x.w);
-    und = ((uint64_t)uh << 32) | ul;
-    return ((uint64_t)ah << 32) | al;
-}
-
-__device__ __forceinline__ uint64_t plane_pair(uint64_t &und, uint64_t eq1, uint32_t T4, uint32_t T8,
-                                               uint32_t p, const U4 &x) {
-    return planes_step(und, eq1, T4, T8, p, x);
+    const uint32_t c = (((T4 >> sa) & 1u) << 3) | (((T8 >> sa) & 1u) << 2) |
+                       (((T4 >> sb) & 1u) << 1) | ((T8 >> sb) & 1u);
+    switch (c) {
+    case 0: plane_pair_case<0>(s, el, eh, x); break;
+    case 1: plane_pair_case<1>(s, el, eh, x); break;
+    case 2: plane_pair_case<2>(s, el, eh, x); break;
+    case 3: plane_pair_case<3>(s, el, eh, x); break;
+    case 4: plane_pair_case<4>(s, el, eh, x); break;
+    case 5: plane_pair_case<5>(s, el, eh, x); break;
+    case 6: plane_pair_case<6>(s, el, eh, x); break;
+    case 7: plane_pair_case<7>(s, el, eh, x); break;
+    case 8: plane_pair_case<8>(s, el, eh, x); break;
+    case 9: plane_pair_case<9>(s, el, eh, x); break;
+    case 10: plane_pair_case<10>(s, el, eh, x); break;
+    case 11: plane_pair_case<11>(s, el, eh, x); break;
+    case 12: plane_pair_case<12>(s, el, eh, x); break;
+    case 13: plane_pair_case<13>(s, el, eh, x); break;
+    case 14: plane_pair_case<14>(s, el, eh, x); break;
+    default: plane_pair_case<15>(s, el, eh, x); break;
+    }
 }
 
 // Ties after the planes: the lanes whose top six uniform bits equal their
@@ -821,11 +850,15 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     // the thresholds are the same for every lane: keep their bits in scalar registers
     const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
+    Lanes s{(uint32_t)und, (uint32_t)(und >> 32), (uint32_t)flip, (uint32_t)(flip >> 32)};
+    const uint32_t el = (uint32_t)eq1, eh = (uint32_t)(eq1 >> 32);
     uint32_t p = 0;
-    for (; und != 0 && p < kPlanePairs; ++p) {
+    for (; (s.ul | s.uh) != 0 && p < kPlanePairs; ++p) {
         const U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
-        flip |= planes_step(und, eq1, T4, T8, p, x);
+        plane_pair(s, el, eh, T4, T8, p, x);
     }
+    und = ((uint64_t)s.uh << 32) | s.ul;
+    flip = ((uint64_t)s.fh << 32) | s.fl;
     uint32_t q = 0;
     for (; und != 0; ++q) {
         const U4 x = philox(k0, k1, w, g, h, kTagTie | q);
@@ -1009,7 +1042,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                         for (uint32_t p = 0; p < kPlanePairs; ++p) {
                             if (und) {
                                 const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagSweep | p);
-                                flip |= plane_pair(und, c.eq1, T4, T8, p, x);
+                                Lanes s{(uint32_t)und, (uint32_t)(und >> 32), (uint32_t)flip,
+                                        (uint32_t)(flip >> 32)};
+                                plane_pair(s, (uint32_t)c.eq1, (uint32_t)(c.eq1 >> 32), T4, T8, p, x);
+                                und = ((uint64_t)s.uh << 32) | s.ul;
+                                flip = ((uint64_t)s.fh << 32) | s.fl;
                                 ++calls;
                             }
                         }
