@@ -929,6 +929,80 @@ __device__ __forceinline__ void walk_advance(WordWalk &w, const WalkStep &s) {
     }
 }
 
+// Bit-sliced counters for the measurement: plane k holds bit k of the 64
+// replicas' counts (one 32-bit half per array).  add() takes the two bond
+// bits and the spin bit of one site word: a full adder puts the two bond bits
+// into the units plane and the carries ripple upwards.  kMeasSites sites per
+// thread keep the bond count <= 16 (5 planes) and the up count <= 8 (4).
+constexpr int kMeasSites = 8;
+constexpr int kPlanesU = 5, kPlanesM = 4;
+
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+
+template <int K>
+__device__ __forceinline__ void ripple(uint32_t (&P)[K], uint32_t c, int from) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k >= from) {
+            const uint32_t t = P[k] & c;
+            P[k] ^= c;
+            c = t;
+        }
+    }
+}
+
+// Butterfly over the 64 lanes: after it every lane holds the sum of all
+// lanes' K-plane counters (one 32-bit half) in K + 6 planes; returns bit
+// `sh` of that sum, i.e. the count of replica sh of this half.
+template <int K>
+__device__ __forceinline__ int wave_count_half(const uint32_t (&p)[K], int sh) {
+    uint32_t a[K + 6];
+#pragma unroll
+    for (int k = 0; k < K + 6; ++k) a[k] = k < K ? p[k] : 0u;
+#pragma unroll
+    for (int lev = 0; lev < 6; ++lev) {
+        const int off = 32 >> lev;
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < K + lev; ++k) {
+            const uint32_t b = __shfl_xor(a[k], off, 64);
+            const uint32_t sum = a[k] ^ b ^ c;
+            c = maj3(a[k], b, c);
+            a[k] = sum;
+        }
+        a[K + lev] = c;
+    }
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < K + 6; ++k) n |= (int)((a[k] >> sh) & 1u) << k;
+    return n;
+}
+
+struct MeasCounters {
+    uint32_t ul[kPlanesU] = {}, uh[kPlanesU] = {}, ml[kPlanesM] = {}, mh[kPlanesM] = {};
+    __device__ __forceinline__ void add(uint64_t a, uint64_t b, uint64_t s) {
+        const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
+        const uint32_t bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+        uint32_t c = maj3(ul[0], al, bl);
+        ul[0] = ul[0] ^ al ^ bl;
+        ripple(ul, c, 1);
+        c = maj3(uh[0], ah, bh);
+        uh[0] = uh[0] ^ ah ^ bh;
+        ripple(uh, c, 1);
+        ripple(ml, (uint32_t)s, 0);
+        ripple(mh, (uint32_t)(s >> 32), 0);
+    }
+    __device__ __forceinline__ void wave_totals(int lane, int *U, int *up) const {
+        const int sh = lane & 31;
+        const int u_lo = wave_count_half<kPlanesU>(ul, sh), u_hi = wave_count_half<kPlanesU>(uh, sh);
+        const int m_lo = wave_count_half<kPlanesM>(ml, sh), m_hi = wave_count_half<kPlanesM>(mh, sh);
+        *U = lane < 32 ? u_lo : u_hi;
+        *up = lane < 32 ? m_lo : m_hi;
+    }
+};
+
 // One block per (run, gpb consecutive groups): the groups' L x L x 64
 // lattices live in LDS as gpb * N words for all theta sweeps (colour 0 then
 // colour 1; a site's index within its colour w = y L/2 + floor(x/2) and the
@@ -1104,22 +1178,39 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         }
     }
 
-    // measurement: lane = replica; waves split the (group, row) pairs
+    // measurement: every thread counts, for its sites of one group, the
+    // antiparallel right and down bonds and the up spins of the group's 64
+    // replicas in bit-sliced counters; the wavefront then sums its 64 threads'
+    // counters (bit-plane butterfly) and lane r adds replica r's totals.
     {
-        const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-        for (int q = wave; q < ng * L; q += nw) {
-            const int gl = q / L, y = q - gl * L;
-            const int base = gl * N, row = base + y * L, dn = (y == L - 1) ? base : row + L;
-            int U = 0, upc = 0;
-            for (int x = 0; x < L; ++x) {
-                const uint64_t w0 = lat[row + x];
-                const uint64_t wr = lat[row + ((x == L - 1) ? 0 : x + 1)];
-                const uint64_t wd = lat[dn + x];
-                U += (int)(((w0 ^ wr) >> lane) & 1ull) + (int)(((w0 ^ wd) >> lane) & 1ull);
-                upc += (int)((w0 >> lane) & 1ull);
+        const int lane = tid & 63;
+        const int dy = nt / L, dx = nt - dy * L;
+        for (int gl = 0; gl < ng; ++gl) {
+            const int base = gl * N;
+            int y = tid / L, x = tid - (tid / L) * L;
+            for (int c0 = 0; c0 < N; c0 += kMeasSites * nt) {  // same trip count in every thread
+                MeasCounters mc;
+#pragma unroll
+                for (int j = 0; j < kMeasSites; ++j) {
+                    if (c0 + j * nt + tid < N) {
+                        const int row = base + y * L;
+                        const uint64_t w0 = lat[row + x];
+                        const uint64_t wr = lat[row + ((x == L - 1) ? 0 : x + 1)];
+                        const uint64_t wd = lat[((y == L - 1) ? base : row + L) + x];
+                        mc.add(w0 ^ wr, w0 ^ wd, w0);
+                    }
+                    x += dx;
+                    y += dy;
+                    if (x >= L) {
+                        x -= L;
+                        ++y;
+                    }
+                }
+                int U, up;
+                mc.wave_totals(lane, &U, &up);
+                atomicAdd(&red_u[gl * kLanes + lane], U);
+                atomicAdd(&red_up[gl * kLanes + lane], up);
             }
-            atomicAdd(&red_u[gl * kLanes + lane], U);
-            atomicAdd(&red_up[gl * kLanes + lane], upc);
         }
     }
     {  // Philox calls of this block (one atomic per wave)
