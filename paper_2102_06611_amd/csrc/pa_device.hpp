@@ -9,6 +9,17 @@
 
 namespace pa {
 
+// Device buffers as global-address-space pointers: loads and stores through
+// them are global (not flat) accesses, which the compiler knows cannot alias
+// LDS, so it can keep several in flight around LDS traffic.
+template <class T>
+using gptr = T __attribute__((address_space(1))) *;
+template <class T>
+__device__ __forceinline__ gptr<T> global(T *p) {
+    return (gptr<T>)p;
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // 16-byte copies
+
 constexpr int kLanes = 64;        // replicas per group = bits per multispin word
 constexpr int kSlotBlock = 1024;  // replica slots per block of the per-slot kernels
 constexpr int kMaxL = 128;

@@ -574,7 +574,7 @@ constexpr int kGatherPg = 4;      // int8: parent groups staged per pass
 constexpr int kGatherSites = 64;  // int8: site rows per pass
 
 __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map) {
-    __shared__ uint4 stage[kGatherPg * kGatherSites * 4];  // int8: groups x rows x 64 bytes
+    __shared__ u32x4 stage[kGatherPg * kGatherSites * 4];  // int8: groups x rows x 64 bytes
     int gd;
     const RunDesc &rd = runs[map_block(map, xcd_swizzle(blockIdx.x, gridDim.x), &gd)];
     RunState *st = rd.st;
@@ -652,8 +652,8 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
     } else {
         // thread -> dword k (children 4k .. 4k + 3) of site rows sl, sl + 16, ...
         // of a chunk of kGatherSites rows
-        const uint4 *src = reinterpret_cast<const uint4 *>(rd.s8[cur]);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(rd.s8[nb] + (size_t)gd * N * kLanes);
+        const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.s8[cur]));
+        const gptr<uint32_t> dst = global(reinterpret_cast<uint32_t *>(rd.s8[nb] + (size_t)gd * N * kLanes));
         const int k = threadIdx.x & 15, sl = threadIdx.x >> 4;
         int pc[4];
 #pragma unroll
@@ -1032,13 +1032,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const int L = rd.L, N = rd.N, half = L >> 1, nb = st->cur ^ 1;
     const int tid = threadIdx.x, nt = blockDim.x;
 
+    // stage the lattices in LDS with 16-byte loads, several in flight per thread
     if (LAYOUT == PA_LAYOUT_MSC64) {
-        const uint64_t *src = rd.ms[nb] + (size_t)g0 * N;
-        for (int w = tid; w < ng * N; w += nt) lat[w] = src[w];
+        const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.ms[nb] + (size_t)g0 * N));
+        u32x4 *l2 = reinterpret_cast<u32x4 *>(lat);
+        const int n2 = ng * N / 2;  // N is even
+#pragma unroll 8
+        for (int w = tid; w < n2; w += nt) l2[w] = src[w];
     } else {
-        const uint4 *src = reinterpret_cast<const uint4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes);
+        const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes));
         uint16_t *l16 = reinterpret_cast<uint16_t *>(lat);
-        for (int it = tid; it < ng * N * 4; it += nt) l16[it] = (uint16_t)pack16(src[it]);
+        const int n16 = ng * N * 4;
+#pragma unroll 8
+        for (int it = tid; it < n16; it += nt) {
+            const u32x4 v = src[it];
+            l16[it] = (uint16_t)pack16(uint4{v.x, v.y, v.z, v.w});
+        }
     }
     for (int k = tid; k < ng * kLanes; k += nt) {
         red_u[k] = 0;
@@ -1229,12 +1238,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     }
     if (theta > 0) {
         if (LAYOUT == PA_LAYOUT_MSC64) {
-            uint64_t *dst = rd.ms[nb] + (size_t)g0 * N;
-            for (int w = tid; w < ng * N; w += nt) dst[w] = lat[w];
+            const gptr<u32x4> dst = global(reinterpret_cast<u32x4 *>(rd.ms[nb] + (size_t)g0 * N));
+            const u32x4 *l2 = reinterpret_cast<const u32x4 *>(lat);
+            for (int w = tid; w < ng * N / 2; w += nt) dst[w] = l2[w];
         } else {
-            uint4 *dst = reinterpret_cast<uint4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes);
+            const gptr<u32x4> dst = global(reinterpret_cast<u32x4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes));
             const uint16_t *l16 = reinterpret_cast<const uint16_t *>(lat);
-            for (int it = tid; it < ng * N * 4; it += nt) dst[it] = unpack16(l16[it]);
+            for (int it = tid; it < ng * N * 4; it += nt) {
+                const uint4 v = unpack16(l16[it]);
+                dst[it] = u32x4{v.x, v.y, v.z, v.w};
+            }
         }
     }
 }
