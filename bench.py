@@ -110,7 +110,12 @@ def time_batch(pa, torch, K):
 
 
 def cpu_baseline(betas, energies):
-    """The oracle, single-threaded, on a bounded sample of the same workload."""
+    """The oracle, single-threaded, on a bounded sample of the same workload.
+
+    Sweeps of one 64-replica group (about 10 s) and one multinomial resampling
+    of the full population at step 101 are timed; the value is the whole-step
+    rate they imply for R = 100000 (theta sweeps of every group plus one
+    resampling per step)."""
     import numpy as np
     from oracle import pa_oracle as po
     beta = betas[-1]
@@ -118,24 +123,26 @@ def cpu_baseline(betas, energies):
     spins = po.init_spins(SEED, L, 64)
     t0 = time.perf_counter()
     sweeps = 0
-    while True:  # sweeps of one 64-replica group until >= 8 s of CPU work
+    while True:  # sweeps of one 64-replica group until >= 10 s of CPU work
         po.sweeps(SEED, L, spins, N_STEPS, 1, t4, t8)
         sweeps += 1
-        if time.perf_counter() - t0 > 8.0 or sweeps >= 200:
+        if time.perf_counter() - t0 > 10.0 or sweeps >= 5000:
             break
     t_sweep = time.perf_counter() - t0
-    attempts = 64 * L * L * sweeps
     o = po.OracleRun(L, 4, THETA, SEED, "multinomial", betas)
     o.R = R
     o.E = np.asarray(energies, dtype=np.int32)
     t1 = time.perf_counter()
     o.copy_counts(betas[100], betas[101], 101)
     t_res = time.perf_counter() - t1
-    return {"value": attempts / t_sweep / 1e9, "unit": "attempts/ns", "cores": 1,
+    groups = math.ceil(R / 64)
+    step_s = t_sweep / sweeps * THETA * groups + t_res
+    return {"value": R * L * L * THETA / step_s / 1e9, "unit": "attempts/ns", "cores": 1,
             "kind": "oracle",
-            "sample": "%d sweeps of 64 replicas (L=64) at beta=%.4f, plus one multinomial "
-                      "resampling of %d parents (%.2f s)" % (sweeps, beta, len(energies), t_res),
-            "resample_s_per_step": t_res, "sweep_seconds": t_sweep}
+            "sample": "%d sweeps of 64 replicas (L=64) at beta=%.4f (%.1f s) and one multinomial "
+                      "resampling of %d parents (%.2f s), scaled to a step of R=%d, theta=%d"
+                      % (sweeps, beta, t_sweep, len(energies), t_res, R, THETA),
+            "step_seconds": step_s, "resample_s_per_step": t_res, "sweep_seconds": t_sweep}
 
 
 def copy_calibration():

@@ -125,3 +125,35 @@ def apply(target, L: int, R: int, layout: str) -> Optional[Tuple[int, int, int]]
         return None
     target.set_sweep_launch(L, e["threads"], e["groups_per_block"], e.get("variant", 0))
     return e["threads"], e["groups_per_block"], e.get("variant", 0)
+
+
+# The workloads the benchmark runs: (L, R, layout, resampling, beta_final, steps)
+WORKLOADS = [
+    (64, 100000, "msc64", "multinomial", 0.4407, 200),
+    (64, 100000, "int8", "multinomial", 0.4407, 200),
+    (128, 100000, "msc64", "nearest", 1.0, 400),
+    (16, 20000, "msc64", "nearest", 0.4407, 200),
+    (32, 20000, "msc64", "nearest", 0.4407, 200),
+    (64, 20000, "msc64", "nearest", 0.4407, 200),
+    (128, 20000, "msc64", "nearest", 0.4407, 200),
+]
+
+
+def main():
+    """Tune every benchmark workload and write the cache.
+
+        python -m paper_2102_06611_amd.autotune
+    """
+    import torch
+    from workloads import linear_schedule
+    torch.cuda.set_device(0)
+    for L, R, layout, resample, beta_f, n in WORKLOADS:
+        e = tune(L, R, layout, linear_schedule(beta_f, n), warm_steps=n // 2, resample=resample)
+        best = sorted(e["candidates"], key=lambda c: c[3])[:4]
+        print("L=%d R=%d %s: %d threads, %d groups/block, variant %d, %.4f ms/sweep phase; best %s"
+              % (L, R, layout, e["threads"], e["groups_per_block"], e["variant"], e["ms_sweep"], best),
+              flush=True)
+
+
+if __name__ == "__main__":
+    main()
