@@ -71,6 +71,7 @@ struct RunDesc {
     double *wlev;              // [2K] per-level Boltzmann factor (double-double, from kmin)
     int32_t *cnt;              // [C] copy counts of the last resampling
     int32_t *off;              // [C + 1] exclusive offsets of the children
+    int32_t *par;              // [C] parent of each child slot of the last resampling
     uint64_t *cum;             // [C] multinomial cumulative quantised weights
     int64_t *part;             // [nblk * 4] per-block partial sums
     double *partd;             // [nblk * 2] per-block FP partials

@@ -390,12 +390,14 @@ __global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap 
 // Multinomial, pass 3: draw d (of R) picks the first parent with
 // cum > floor(U64_d * W / 2^64); counts accumulate atomically (order-free).
 // The search first runs over every 64th cumulative weight, held in LDS, and
-// then over the at most 64 parents of the chosen stretch.
+// then over the at most 64 parents of the chosen stretch.  Four blocks share
+// each slot block's 1024 draws (one draw per thread).
 constexpr int kCoarse = 4096;
+constexpr int kDrawSplit = kSlotBlock / 256;
 
 __global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap map) {
     int b;
-    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    const RunDesc &rd = runs[map_block(map, blockIdx.x / kDrawSplit, &b)];
     RunState *st = rd.st;
     if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
     __shared__ uint64_t coarse[kCoarse];
@@ -403,35 +405,32 @@ __global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap
     const uint64_t W = st->w_total;
     const int nc = (Rp + 63) >> 6;  // stretch k covers parents [64k, 64k + 63]
     const bool use_coarse = nc <= kCoarse;
-    if (use_coarse)
-        for (int k = threadIdx.x; k < nc; k += blockDim.x) coarse[k] = rd.cum[min(64 * k + 63, Rp - 1)];
-    __syncthreads();
-    const int d0 = b * kSlotBlock + 4 * (int)threadIdx.x;
-    for (int h = 0; h < 2; ++h) {
-        const int d = d0 + 2 * h;
-        if (d >= rd.R) break;
-        const U4 x = philox(rd.key0, rd.key1, (uint32_t)(d >> 1), (uint32_t)i, 0u, kTagMulti);
-        const uint64_t U[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
-        for (int m = 0; m < 2; ++m) {
-            if (d + m >= rd.R) break;
-            const uint64_t target = mulhi64(U[m], W);
-            int lo = 0, hi = Rp - 1;  // first j with cum[j] > target
-            if (use_coarse) {
-                int cl = 0, ch = nc - 1;  // first stretch whose last weight exceeds target
-                while (cl < ch) {
-                    const int mid = (cl + ch) >> 1;
-                    if (coarse[mid] > target) ch = mid; else cl = mid + 1;
-                }
-                lo = 64 * cl;
-                hi = min(64 * cl + 63, Rp - 1);
-            }
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (rd.cum[mid] > target) hi = mid; else lo = mid + 1;
-            }
-            atomicAdd(&rd.cnt[lo], 1);
-        }
+    const gptr<const uint64_t> cum = global(static_cast<const uint64_t *>(rd.cum));
+    if (use_coarse) {
+#pragma unroll 8
+        for (int k = threadIdx.x; k < nc; k += blockDim.x) coarse[k] = cum[min(64 * k + 63, Rp - 1)];
     }
+    __syncthreads();
+    const int d = b * kSlotBlock + (int)(blockIdx.x % kDrawSplit) * 256 + (int)threadIdx.x;
+    if (d >= rd.R) return;
+    const U4 x = philox(rd.key0, rd.key1, (uint32_t)(d >> 1), (uint32_t)i, 0u, kTagMulti);
+    const uint64_t U = (d & 1) ? ((uint64_t)x.w << 32) | x.z : ((uint64_t)x.y << 32) | x.x;
+    const uint64_t target = mulhi64(U, W);
+    int lo = 0, hi = Rp - 1;  // first j with cum[j] > target
+    if (use_coarse) {
+        int cl = 0, ch = nc - 1;  // first stretch whose last weight exceeds target
+        while (cl < ch) {
+            const int mid = (cl + ch) >> 1;
+            if (coarse[mid] > target) ch = mid; else cl = mid + 1;
+        }
+        lo = 64 * cl;
+        hi = min(64 * cl + 63, Rp - 1);
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cum[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    atomicAdd(&rd.cnt[lo], 1);
 }
 
 // Multinomial, pass 4: block partials of the counts (as k_counts_nearest).
@@ -458,7 +457,7 @@ __global__ void __launch_bounds__(256) k_count_partials(const RunDesc *runs, Wor
 }
 
 // off[j] = sum_{l<j} r_l (children of parent j occupy [off[j], off[j] + r_j)),
-// off[R_{i-1}] = R_i.  Block 0 records R_i (or PA_ERR_CAPACITY) and
+// off[R_{i-1}] = R_i, and par[c] = j for those children.  Block 0 records R_i (or PA_ERR_CAPACITY) and
 // sum r_j^2.  The histogram, consumed by k_norm, is cleared here so that the
 // reduction at the end of the step can build the next one.
 __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap map) {
@@ -497,7 +496,12 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
     int64_t tot;
     int64_t run = base_sh + block_exclusive_scan(c[0] + c[1] + c[2] + c[3], sh, &tot);
     for (int m = 0; m < 4; ++m) {
-        if (j + m < Rp) rd.off[j + m] = (int32_t)run;
+        if (j + m < Rp) {
+            rd.off[j + m] = (int32_t)run;
+            // the parent of each child slot (past the capacity the step fails anyway)
+            const gptr<int32_t> par = global(rd.par);
+            for (int64_t k = run; k < run + c[m] && k < rd.C; ++k) par[k] = j + m;
+        }
         run += c[m];
     }
 }
@@ -584,15 +588,7 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
     const int cur = st->cur, nb = cur ^ 1, N = rd.N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int c = gd * kLanes + lane;
-    int p = -1;
-    if (c < Rn) {
-        int lo = 0, hi = Rp;  // off[0..Rp] is non-decreasing, off[0] = 0 <= c < off[Rp]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (rd.off[mid] <= c) lo = mid; else hi = mid - 1;
-        }
-        p = lo;
-    }
+    const int p = c < Rn ? rd.par[c] : -1;  // the last j with off[j] <= c
     if (wave == 0 && c < rd.C) rd.fam[nb][c] = p >= 0 ? rd.fam[cur][p] : 0;
     const int nv = __builtin_amdgcn_readfirstlane(min(kLanes, Rn - gd * kLanes));
     const int g_first = __builtin_amdgcn_readlane(p, 0) >> 6;
@@ -1553,7 +1549,7 @@ hipError_t launch_resample(const LaunchCtx &c) {
                   c.slots.map);
         PA_LAUNCH(k_multi_cum, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
-        PA_LAUNCH(k_multi_draw, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
+        PA_LAUNCH(k_multi_draw, dim3(c.slots.total * kDrawSplit), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
         PA_LAUNCH(k_count_partials, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
