@@ -315,8 +315,11 @@ class OracleRun:
                 return np.ones(Rp, dtype=np.int32), ln_q
             if self.resample == "nearest":
                 counts = np.zeros(Rp, dtype=np.int32)
+                single_level = len(boltz) == 1
                 for j in range(Rp):
-                    tau = boltz[int(E[j])] / Q  # tau_i(E_j)
+                    # tau_i(E_j); with one energy level every replica's weight equals Q,
+                    # so tau = 1 exactly (a floating evaluation would only be close to it)
+                    tau = mpmath.mpf(1) if single_level else boltz[int(E[j])] / Q
                     tau_hat = mpmath.mpf(self.R) / Rp * tau  # Eq. (taus)
                     _check_margin(mpmath.ldexp(tau_hat, 32), "2^32 tau_hat")
                     fl = mpmath.floor(tau_hat)
