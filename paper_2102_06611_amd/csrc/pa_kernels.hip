@@ -1251,48 +1251,42 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 // ------------------------------------------------------------------ reduction + record
 
 // Population sums over the R_i replicas and family statistics from the
-// tree-ordered labels: families are contiguous runs, a run ending at slot c
-// has length c - first(c) + 1.  first(c) comes from a block max-scan of the
-// run starts; a run entering the block from the left is located once per
-// block by binary search.  The block also adds its slots to the energy
-// histogram that the next step's k_norm reads.  Partials go to part[b*8 + k],
-// partd[b*2]; k_record combines them.
+// tree-ordered labels: families are contiguous runs of equal labels.  Each
+// block of kSlotBlock slots finds its runs (a block max-scan of the run starts)
+// and sums f, sum len^2 and sum len ln len over the runs that lie inside it;
+// a run that crosses the block's first or last slot is reported as a portion
+// (first_len / last_len with continuation flags) for k_record to stitch.  The
+// block also adds its slots to the energy histogram that the next step's
+// k_norm reads.  Partials go to part[b*8 + k] (k = 0..7) and partd[b*2].
+constexpr int64_t kRunContPrev = 1ll << 32, kRunContNext = 1ll << 33, kRunSingle = 1ll << 34;
+
 __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
     if (st->err) return;
-    __shared__ int64_t sh[32];
-    __shared__ double shd[32];
-    __shared__ int first_start;
+    __shared__ int64_t shv[4][6];
+    __shared__ double shd[4];
+    __shared__ int wmax[16];
+    __shared__ int64_t edge[2];
     const int Rn = st->R_new, nb = st->cur ^ 1;
     const int32_t *fam = rd.fam[nb];
     const int j0 = b * kSlotBlock, j1 = min(j0 + kSlotBlock, Rn);
+    const bool cont_prev = j0 > 0 && j0 < Rn && fam[j0 - 1] == fam[j0];
+    const bool cont_next = j1 > j0 && j1 < Rn && fam[j1] == fam[j1 - 1];
     if (threadIdx.x == 0) {
-        int s0 = 0;
-        if (j0 < Rn && j0 > 0 && fam[j0 - 1] == fam[j0]) {
-            int lo = 0, hi = j0;  // first slot with fam == fam[j0]
-            const int fc = fam[j0];
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (fam[mid] < fc) lo = mid + 1; else hi = mid;
-            }
-            s0 = lo;
-        } else {
-            s0 = j0;
-        }
-        first_start = s0;
+        edge[0] = 0;
+        edge[1] = 0;
     }
-    __syncthreads();
     // each thread owns 4 consecutive slots
     const int c0 = j0 + 4 * (int)threadIdx.x;
     int last_start = -1;  // start of the run containing the thread's last slot, within the thread
-    int starts[4];
+    bool is_start[4];
+#pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int c = c0 + m;
-        starts[m] = -1;
-        if (c < j1 && (c == j0 || fam[c - 1] != fam[c])) starts[m] = (c == j0) ? first_start : c;
-        if (starts[m] >= 0) last_start = starts[m];
+        is_start[m] = c < j1 && (c == j0 || fam[c - 1] != fam[c]);
+        if (is_start[m]) last_start = c;
     }
     // exclusive max-scan of last_start over threads gives the run start entering each thread
     int x = last_start;
@@ -1302,7 +1296,6 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
         const int y = __shfl_up(x, o, 64);
         if (lane >= o) x = max(x, y);
     }
-    __shared__ int wmax[16];
     if (lane == 63) wmax[wave] = x;
     __syncthreads();
     int prev = -1;
@@ -1312,29 +1305,53 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     int64_t sE = 0, sE2 = 0, sM = 0, sM2 = 0, f = 0, s2 = 0;
     double cl = 0.0;
     int run_start = prev;
+#pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int c = c0 + m;
         if (c >= j1) break;
-        if (starts[m] >= 0) run_start = starts[m];
+        if (is_start[m]) run_start = c;
         const int64_t e = rd.E[c], mm = rd.M[c];
         sE += e;
         sE2 += e * e;
         sM += mm < 0 ? -mm : mm;
         sM2 += mm * mm;
-        if (c == Rn - 1 || fam[c + 1] != fam[c]) {
+        if (c == j1 - 1 || fam[c + 1] != fam[c]) {  // a run ends at c
             const int64_t len = c - run_start + 1;
-            f += 1;
-            s2 += len * len;
-            cl += (double)len * log((double)len);
+            const bool first = run_start == j0, last = c == j1 - 1;
+            if ((first && cont_prev) || (last && cont_next)) {
+                if (first) edge[0] = len | (cont_prev ? kRunContPrev : 0) |
+                                     (cont_next ? kRunContNext : 0) | (last ? kRunSingle : 0);
+                if (last) edge[1] = len;
+            } else {
+                f += 1;
+                s2 += len * len;
+                cl += (double)len * log((double)len);
+            }
         }
     }
     const int64_t v[6] = {sE, sE2, sM, sM2, f, s2};
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const int64_t t = block_sum_i64(v[k], sh);
-        if (threadIdx.x == 0) rd.part[b * 8 + k] = t;
+        const int64_t t = wave_sum_i64(v[k]);
+        if (lane == 0) shv[wave][k] = t;
     }
-    const double tcl = block_sum_f64(cl, shd);
-    if (threadIdx.x == 0) rd.partd[b * 2] = tcl;
+    const double tcl = wave_sum_f64(cl);
+    if (lane == 0) shd[wave] = tcl;
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        int64_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += shv[w][threadIdx.x];
+        rd.part[b * 8 + threadIdx.x] = t;
+    } else if (threadIdx.x == 6) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += shd[w];
+        rd.partd[b * 2] = t;
+    } else if (threadIdx.x == 7) {
+        // a first run that continues from the previous block but not past this
+        // one is marked in edge[0]; an open last run in edge[1]
+        rd.part[b * 8 + 6] = edge[0] | (cont_next ? kRunContNext : 0) | (cont_prev ? kRunContPrev : 0);
+        rd.part[b * 8 + 7] = edge[1];
+    }
     block_histogram(rd, st, j0, j1);
 }
 
@@ -1349,9 +1366,35 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     __shared__ double shd[32];
     const int Rn = st->R_new, nb = st->cur ^ 1;
     const int nblk = (Rn + kSlotBlock - 1) / kSlotBlock;
+    // runs that cross block boundaries: every block in which such a run ends
+    // walks back over the blocks it spans (each lies wholly inside the run)
+    // to the block where it started, and adds its length
+    int64_t fx = 0, s2x = 0;
+    double clx = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+        const int64_t e0 = rd.part[k * 8 + 6];
+        const bool cp = (e0 & kRunContPrev) != 0, cn = (e0 & kRunContNext) != 0;
+        const bool single = (e0 & kRunSingle) != 0;
+        if (!cp || (single && cn)) continue;  // no crossing run ends here
+        int64_t len = e0 & 0xFFFFFFFFll;
+        for (int q = k - 1; q >= 0; --q) {
+            const int64_t eq = rd.part[q * 8 + 6];
+            if ((eq & kRunSingle) && (eq & kRunContPrev)) {
+                len += eq & 0xFFFFFFFFll;
+            } else {
+                len += rd.part[q * 8 + 7];
+                break;
+            }
+        }
+        fx += 1;
+        s2x += len * len;
+        clx += (double)len * log((double)len);
+    }
     int64_t T[6];
     for (int q = 0; q < 6; ++q) T[q] = block_sum_partials(rd, q, nblk, sh);
-    double c = 0.0;
+    T[4] += block_sum_i64(fx, sh);
+    T[5] += block_sum_i64(s2x, sh);
+    double c = clx;
     for (int k = threadIdx.x; k < nblk; k += blockDim.x) c += rd.partd[k * 2];
     const double TCL = block_sum_f64(c, shd);
     if (threadIdx.x != 0) return;

@@ -97,6 +97,10 @@ CASES = [
     (8, 300, 0, 5, 0.8, "nearest", "msc64"),
     (16, 150, 2, 4, 0.44, "multinomial", "msc64"),
     (12, 100, 2, 4, 2.0, "none", "int8"),
+    # several 1024-slot blocks and strong selection: families span block
+    # boundaries (the first grows one family over five blocks)
+    (6, 5000, 0, 6, 2.0, "nearest", "msc64"),
+    (4, 5000, 1, 6, 3.0, "multinomial", "int8"),
 ]
 
 
