@@ -197,6 +197,25 @@ __device__ __forceinline__ dd dd_ldexp(dd a, int e) { return dd{ldexp(a.hi, e), 
 // ln 2 to ~107 bits.
 __device__ __forceinline__ dd dd_ln2() { return dd{6.93147180559945286227e-01, 2.31904681384629955842e-17}; }
 
+// 1/n for n = 1..14 as double-double (hi + lo, |lo| <= ulp(hi)/2): the Taylor
+// terms multiply by these instead of dividing.
+__device__ constexpr dd kRecip[14] = {
+    {0x1.0000000000000p+0, 0x0.0p+0},  // 1/1
+    {0x1.0000000000000p-1, 0x0.0p+0},  // 1/2
+    {0x1.5555555555555p-2, 0x1.5555555555555p-56},  // 1/3
+    {0x1.0000000000000p-2, 0x0.0p+0},  // 1/4
+    {0x1.999999999999ap-3, -0x1.999999999999ap-57},  // 1/5
+    {0x1.5555555555555p-3, 0x1.5555555555555p-57},  // 1/6
+    {0x1.2492492492492p-3, 0x1.2492492492492p-57},  // 1/7
+    {0x1.0000000000000p-3, 0x0.0p+0},  // 1/8
+    {0x1.c71c71c71c71cp-4, 0x1.c71c71c71c71cp-58},  // 1/9
+    {0x1.999999999999ap-4, -0x1.999999999999ap-58},  // 1/10
+    {0x1.745d1745d1746p-4, -0x1.745d1745d1746p-59},  // 1/11
+    {0x1.5555555555555p-4, 0x1.5555555555555p-58},  // 1/12
+    {0x1.3b13b13b13b14p-4, -0x1.3b13b13b13b14p-58},  // 1/13
+    {0x1.2492492492492p-4, 0x1.2492492492492p-58},  // 1/14
+};
+
 // exp(-x) for x >= 0 given in double-double.  Returns false (and sets *out to
 // 0) when exp(-x) < 2^-1000, i.e. far below every decision boundary here.
 // Range reduction x = k ln 2 + r, |r| <= ln 2 / 2; then r / 16 and a Taylor
@@ -211,8 +230,9 @@ __device__ inline bool dd_exp_neg(dd x, dd *out) {
     dd rs = dd_ldexp(dd_neg(r), -4);          // -r / 16
     dd term = dd{1.0, 0.0};
     dd sum = dd{1.0, 0.0};
+#pragma unroll
     for (int n = 1; n <= 14; ++n) {
-        term = dd_div_d(dd_mul(term, rs), (double)n);
+        term = dd_mul(dd_mul(term, rs), kRecip[n - 1]);  // term_n = term_{n-1} (-r/16) / n
         sum = dd_add(sum, term);
     }
     for (int s = 0; s < 4; ++s) sum = dd_mul(sum, sum);

@@ -214,14 +214,21 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     const int nlev = kmax - kmin + 1;
     const dd db = two_sum(rd.betas[i], -rd.betas[i - 1]);
     const bool exact = (db.hi == 0.0) || (nlev == 1);
+    // w_l = exp(-4 dbeta l): the thread's first level by exp, then repeated
+    // multiplication by exp(-4 dbeta blockDim) (at most nlev / blockDim double-
+    // double products, relative error far below the decision margin)
     dd part{0.0, 0.0};
+    dd w{1.0, 0.0}, stride{1.0, 0.0};
+    if (!exact) {
+        if (threadIdx.x > 0) dd_exp_neg(dd_mul_d(db, 4.0 * threadIdx.x), &w);
+        dd_exp_neg(dd_mul_d(db, 4.0 * blockDim.x), &stride);
+    }
     for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
-        dd w{1.0, 0.0};
-        if (!exact && l > 0) dd_exp_neg(dd_mul_d(db, 4.0 * l), &w);
         rd.wlev[2 * l] = w.hi;
         rd.wlev[2 * l + 1] = w.lo;
         int n = rd.hist[kmin + l];
         if (n) part = dd_add(part, dd_mul_d(w, (double)n));
+        if (!exact) w = dd_mul(w, stride);
     }
     sh_hi[threadIdx.x] = part.hi;
     sh_lo[threadIdx.x] = part.lo;
