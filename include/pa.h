@@ -192,13 +192,12 @@ pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, do
                           double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words);
 
 /* Launch geometry of the sweep kernel for the runs of lattice side L: threads
- * per block (a multiple of 64 in [64, 1024]), 64-replica groups per block
- * (1..8, with groups_per_block * L^2 * 8 bytes <= 152 KiB of LDS) and the
- * variant of the plane-by-plane comparison: 0 runs each word's comparison to
- * the end in its own lane, 1 pools the words still undecided after three
- * Philox calls in per-wavefront lists.  The results do not depend on any of
- * it (the random numbers are keyed by replica and site); only speed does.
- * Synchronises. */
+ * per block (a multiple of 64 in [64, 1024]) and 64-replica groups per block
+ * (1..8, with groups_per_block * (L + 2)^2 * 8 bytes <= 152 KiB of LDS: each
+ * lattice is held with a one-site halo).  variant must be 0 (PA_ERR_ARG
+ * otherwise; reserved for other comparison schedules).  The results do not
+ * depend on the geometry (the random numbers are keyed by replica and site);
+ * only speed does.  Synchronises. */
 pa_status pa_set_sweep_launch(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_block,
                               int32_t variant);
 pa_status pa_get_sweep_launch(pa_ctx *ctx, int32_t L, int32_t *threads, int32_t *groups_per_block,

@@ -2,7 +2,8 @@
 
 The sweep kernel keeps whole 64-replica lattices in LDS; its free parameters
 are the threads per block and the number of 64-replica groups per block
-(small lattices leave threads idle unless several groups share a block).  The
+(small lattices leave threads idle unless several groups share a block);
+the variant field of the ABI is kept at 0.  The
 random numbers are keyed by replica and site, so every geometry must produce
 the same population: the tuner checks that bit for bit while it times each
 candidate from one snapshot, and stores the fastest per (arch, L, R bucket,
@@ -39,19 +40,17 @@ def key(L: int, R: int, layout: str) -> str:
 
 
 def candidates(L: int) -> List[Tuple[int, int, int]]:
-    """(threads, groups per block, comparison variant) triples worth timing."""
+    """(threads, groups per block, variant) triples worth timing (variant is 0)."""
     N = L * L
+    lds = (L + 2) * (L + 2) * 8  # one lattice with its halo
     out = []
     for gpb in (1, 2, 4, 8):
-        if gpb * N * 8 > MAX_LDS:
+        if gpb * lds > MAX_LDS:
             continue
         if gpb > 1 and (gpb // 2) * N // 2 >= 1024:
             continue  # one group already fills a 1024-thread block
         for threads in (128, 256, 512, 1024):
-            if gpb * N * 8 + (threads // 64) * 2 * 64 * 10 > MAX_LDS:
-                continue
-            for variant in (0, 1):
-                out.append((threads, gpb, variant))
+            out.append((threads, gpb, 0))
     return out
 
 

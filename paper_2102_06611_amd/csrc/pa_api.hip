@@ -209,16 +209,12 @@ void dd_n_ln2(int N, double *hi, double *lo) {
     *lo = e - (s - p);
 }
 
-// Default sweep geometry: enough 64-replica groups per block for ~512 words
-// per half-sweep (small lattices), and 1024 threads when a block's LDS is so
-// large that only one block fits on a CU.
+// Default sweep geometry (what the autotuner finds on gfx950 for the usual
+// population sizes): one 64-replica group per block, 128 threads for L <= 16,
+// 512 up to L = 64 and 1024 above, where a lattice fills most of a CU's LDS.
 void default_sweep_launch(int L, int *threads, int *gpb) {
-    const int N = L * L;
-    int g = 512 / (N / 2);
-    g = std::max(1, std::min(8, g));
-    while (g > 1 && (size_t)g * N * 8 > (size_t)kMaxSweepLds) --g;
-    *gpb = g;
-    *threads = ((size_t)g * N * 8 > 80 * 1024) ? 512 : 256;
+    *gpb = 1;
+    *threads = L <= 16 ? 128 : (L <= 64 ? 512 : 1024);
 }
 
 std::once_flag g_config_once;
@@ -415,7 +411,6 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         sc.has_msc = c.msc;
         sc.has_int8 = c.i8;
         default_sweep_launch(c.L, &sc.threads, &sc.gpb);
-        sc.pooled = 0;
         lc.sweep_classes.push_back(sc);
     }
     for (size_t k = 0; k < lc.sweep_classes.size(); ++k) {
@@ -858,16 +853,15 @@ static pa_status set_sweep_launch(pa_batch *B, int32_t L, int32_t threads, int32
     if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
     if (threads < 64 || threads > 1024 || threads % 64) return fail(B, PA_ERR_ARG, "threads must be a multiple of 64 in [64, 1024]");
     if (gpb < 1 || gpb > 8) return fail(B, PA_ERR_ARG, "groups_per_block must be in [1, 8]");
-    if (variant < 0 || variant > 1) return fail(B, PA_ERR_ARG, "variant must be 0 or 1");
-    if (sweep_lds_bytes(L * L, gpb, threads, 1) > (size_t)kMaxSweepLds)
-        return fail(B, PA_ERR_ARG, "groups_per_block * L^2 * 8 plus the word lists exceed the LDS budget");
+    if (variant != 0) return fail(B, PA_ERR_ARG, "variant must be 0");
+    if (sweep_lds_bytes(L, gpb) > (size_t)kMaxSweepLds)
+        return fail(B, PA_ERR_ARG, "groups_per_block * (L + 2)^2 * 8 bytes exceed the LDS budget");
     for (size_t k = 0; k < B->lc.sweep_classes.size(); ++k) {
         SweepClass &sc = B->lc.sweep_classes[k];
         if (sc.L != L) continue;
         PA_HIP(B, hipStreamSynchronize(B->stream));
         sc.threads = threads;
         sc.gpb = gpb;
-        sc.pooled = variant;
         pa_status e = upload_class_map(B, (int)k);
         if (e) return e;
         PA_HIP(B, hipStreamSynchronize(B->stream));
@@ -889,7 +883,7 @@ static pa_status get_sweep_launch(pa_batch *B, int32_t L, int32_t *threads, int3
         if (sc.L != L) continue;
         if (threads) *threads = sc.threads;
         if (gpb) *gpb = sc.gpb;
-        if (variant) *variant = sc.pooled;
+        if (variant) *variant = 0;
         return PA_OK;
     }
     return fail(B, PA_ERR_ARG, "no run with this L");

@@ -21,7 +21,6 @@ struct SweepClass {
     bool has_msc, has_int8;
     int threads;  // block size of k_sweep for this lattice size
     int gpb;      // 64-replica groups per block
-    int pooled;   // 1: undecided words pooled per wavefront; 0: lane-local comparisons
 };
 
 struct LaunchCtx {
@@ -35,8 +34,7 @@ struct LaunchCtx {
 };
 
 hipError_t configure_kernels();
-size_t sweep_lds_bytes(int N, int gpb, int threads, int cpl);
-int sweep_cpl(int N, int gpb, int threads);
+size_t sweep_lds_bytes(int L, int gpb);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 hipError_t launch_init(const LaunchCtx &c);
 hipError_t launch_sweeps(const LaunchCtx &c, int init);

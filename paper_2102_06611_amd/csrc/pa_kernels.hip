@@ -706,16 +706,6 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
 // Bit-sliced Metropolis classes of one word (64 replicas of one site): with
 // a_k = s XOR n_k (antiparallel neighbours), A = sum a_k and dE = 8 - 4A,
 // A >= 2 (dE <= 0) always flips, A = 1 is dE = 4, A = 0 is dE = 8.
-struct WordClass {
-    uint64_t ge2, eq1, eq0;
-};
-__device__ __forceinline__ WordClass classify(uint64_t a1, uint64_t a2, uint64_t a3, uint64_t a4) {
-    const uint64_t x12 = a1 ^ a2, y12 = a1 & a2, x34 = a3 ^ a4, y34 = a3 & a4;
-    const uint64_t ge2 = y12 | y34 | (x12 & x34);
-    const uint64_t any = x12 | y12 | x34 | y34;
-    return WordClass{ge2, any & ~ge2, ~any};
-}
-
 // The same classes per 32-bit half with three-input operations: with m =
 // maj(a1, a2, a3) and o = a1 | a2 | a3, A >= 2 is m | (a4 & o) and A = 1 is
 // (o | a4) & ~(A >= 2).
@@ -871,64 +861,73 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     return flip;
 }
 
-// Position of a word of one colour inside the block's lattices: word index
-// idx -> (group gl, row y, half-column xh), lattice offsets of the site and its
-// four neighbours (reciprocal multiply with a one-step correction).
-struct WordPos {
-    int gl, wi, site, r, l, u, d;
+// The block's lattices in LDS carry a halo: group gl's site (x, y) is word
+// gl A + (y + 1) P + x + 1 with row pitch P = L + 2 and A = (L + 2) P words
+// per group, and the ghost columns x = -1, L and rows y = -1, L hold copies
+// of the opposite edge (periodic boundaries), so that the four neighbours of
+// every site sit at -1, +1, -P and +P.
+struct Halo {
+    int L, P, A;
+    __device__ __forceinline__ int at(int gl, int x, int y) const { return gl * A + (y + 1) * P + x + 1; }
 };
-__device__ __forceinline__ WordPos word_pos(int idx, int colour, int L, int N, int half,
-                                            float inv_half, float inv_L) {
-    int r = (int)((float)idx * inv_half);
-    int xh = idx - r * half;
-    if (xh >= half) { ++r; xh -= half; }
-    if (xh < 0) { --r; xh += half; }
-    int gl = (int)((float)r * inv_L);
-    int y = r - gl * L;
-    if (y >= L) { ++gl; y -= L; }
-    if (y < 0) { --gl; y += L; }
-    const int x = 2 * xh + ((colour + y) & 1);
-    const int base = gl * N;
-    const int row = base + y * L;
-    WordPos w;
-    w.gl = gl;
-    w.wi = y * half + xh;
-    w.site = row + x;
-    w.r = row + ((x == L - 1) ? 0 : x + 1);
-    w.l = row + ((x == 0) ? L - 1 : x - 1);
-    w.u = ((y == 0) ? base + N - L : row - L) + x;
-    w.d = ((y == L - 1) ? base : row + L) + x;
-    return w;
+__device__ __forceinline__ Halo halo(int L) { return Halo{L, L + 2, (L + 2) * (L + 2)}; }
+
+// Copy the edges of every group's lattice into its ghost cells: item k of
+// ng 4L items copies edge site src into ghost dst.  A thread's items are fixed
+// for the whole kernel; the first one is kept in registers (HaloItem), the
+// rest (only when 4 L ng exceeds the block) are recomputed.
+struct HaloItem {
+    int src, dst;  // -1: none
+};
+__device__ __forceinline__ HaloItem halo_item(const Halo &hl, int k) {
+    const int L = hl.L, gl = k / (4 * L), r = k - gl * 4 * L, side = r / L, t = r - side * L;
+    if (side == 0) return HaloItem{hl.at(gl, L - 1, t), hl.at(gl, -1, t)};
+    if (side == 1) return HaloItem{hl.at(gl, 0, t), hl.at(gl, L, t)};
+    if (side == 2) return HaloItem{hl.at(gl, t, L - 1), hl.at(gl, t, -1)};
+    return HaloItem{hl.at(gl, t, 0), hl.at(gl, t, L)};
+}
+__device__ __forceinline__ void fill_halo(uint64_t *lat, const Halo &hl, int ng, const HaloItem &mine) {
+    if (mine.src >= 0) lat[mine.dst] = lat[mine.src];
+    for (int k = threadIdx.x + blockDim.x; k < ng * 4 * hl.L; k += blockDim.x) {
+        const HaloItem it = halo_item(hl, k);
+        lat[it.dst] = lat[it.src];
+    }
 }
 
 // Incremental walk over the words idx, idx + nt, ... of one colour: half-column
 // xh = idx mod L/2 and global row r = idx div L/2 = gl L + y, kept as (xh, y,
-// gl, row = r L) and advanced by nt words with one carry each, so that no
-// division is needed per word.
+// gl, row = the halo index of (0, y) in group gl) and advanced by nt words
+// with one carry each, so that no division is needed per word.
 struct WordWalk {
     int xh, y, gl, row;
 };
 struct WalkStep {
-    int half, L, dxh, dy, dgl, drow;  // nt = (dgl L + dy) half + dxh, drow = (dgl L + dy) L
+    int half, L, P, dxh, dy, dgl, drow, wrap;  // stride = (dgl L + dy) half + dxh; half = units per row
 };
-__device__ __forceinline__ WalkStep walk_step(int nt, int half, int L) {
-    const int dr = nt / half;
-    return WalkStep{half, L, nt - dr * half, dr % L, dr / L, dr * L};
+// units = positions per row: L/2 for the words of one colour (and for pairs of
+// sites), L for single sites (then xh is the column)
+__device__ __forceinline__ WalkStep walk_step(int nt, const Halo &hl, int units) {
+    const int dr = nt / units, dy = dr % hl.L, dgl = dr / hl.L;
+    return WalkStep{units, hl.L, hl.P, nt - dr * units, dy, dgl, dgl * hl.A + dy * hl.P,
+                    hl.A - hl.L * hl.P};
 }
-__device__ __forceinline__ WordWalk walk_start(int idx, int half, int L) {
-    const int r = idx / half;
-    return WordWalk{idx - r * half, r % L, r / L, r * L};
+__device__ __forceinline__ WalkStep walk_step(int nt, const Halo &hl) { return walk_step(nt, hl, hl.L >> 1); }
+__device__ __forceinline__ WordWalk walk_start(int idx, const Halo &hl, int units) {
+    const int r = idx / units, y = r % hl.L, gl = r / hl.L;
+    return WordWalk{idx - r * units, y, gl, hl.at(gl, 0, y)};
 }
+__device__ __forceinline__ WordWalk walk_start(int idx, const Halo &hl) { return walk_start(idx, hl, hl.L >> 1); }
 __device__ __forceinline__ void walk_advance(WordWalk &w, const WalkStep &s) {
     w.xh += s.dxh;
     const int c = w.xh >= s.half ? 1 : 0;
     w.xh -= c ? s.half : 0;
-    w.row += s.drow + (c ? s.L : 0);
+    w.row += s.drow + (c ? s.P : 0);
     w.y += s.dy + c;
     w.gl += s.dgl;
     if (w.y >= s.L) {
         w.y -= s.L;
         w.gl += 1;
+        w.row += s.wrap;
     }
 }
 
@@ -1007,21 +1006,18 @@ struct MeasCounters {
 };
 
 // One block per (run, gpb consecutive groups): the groups' L x L x 64
-// lattices live in LDS as gpb * N words for all theta sweeps (colour 0 then
-// colour 1; a site's index within its colour w = y L/2 + floor(x/2) and the
-// global half-sweep index h = 2 (theta (i-1) + sweep) + colour key its random
-// bits).  Variant 0 (lane-local) runs each word's whole comparison in one
-// lane.  Variant 1 (pooled) takes a half-sweep's words in batches of cpl per
-// lane: every word first gets its plane calls in its own lane; the words with
-// lanes still tied go to a per-wavefront list, which all 64 lanes then work
-// through one tie call per round.  Afterwards each replica's E = 2U - 2N (U
-// antiparallel bonds) and M are measured.  With init != 0 no sweep is done.
+// lattices live in LDS (with a halo, see Halo) for all theta sweeps (colour 0
+// then colour 1; a site's index within its colour w = y L/2 + floor(x/2) and
+// the global half-sweep index h = 2 (theta (i-1) + sweep) + colour key its
+// random bits).  Each word's whole comparison runs in one lane; a thread walks
+// the words tid, tid + nt, ... of a colour.  After each half-sweep the ghost
+// cells are refreshed.  Afterwards each replica's E = 2U - 2N (U antiparallel
+// bonds) and M are measured.  With init != 0 no sweep is done.
 constexpr int kMaxGroupsPerBlock = 8;
 
-
-template <int LAYOUT, int POOLED>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_sweep(const RunDesc *runs, WorkMap map, int init,
-                                                int gpb, int cpl) {
+template <int LAYOUT>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     extern __shared__ uint64_t lat[];
     __shared__ int32_t red_u[kMaxGroupsPerBlock * kLanes], red_up[kMaxGroupsPerBlock * kLanes];
     int bi;
@@ -1034,158 +1030,78 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const int ng = min(gpb, (Rn + kLanes - 1) / kLanes - g0);  // groups with live replicas
     const int L = rd.L, N = rd.N, half = L >> 1, nb = st->cur ^ 1;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const Halo hl = halo(L);
 
-    // stage the lattices in LDS with 16-byte loads, several in flight per thread
+    // stage the lattices in LDS: 16-byte loads (two words of one row), several
+    // in flight per thread; pair w = (row, half-column) is walked like a word
+    // of one colour (L is even: a pair never crosses a row)
+    const WalkStep step = walk_step(nt, hl);
     if (LAYOUT == PA_LAYOUT_MSC64) {
         const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.ms[nb] + (size_t)g0 * N));
-        u32x4 *l2 = reinterpret_cast<u32x4 *>(lat);
-        const int n2 = ng * N / 2;  // N is even
-#pragma unroll 8
-        for (int w = tid; w < n2; w += nt) l2[w] = src[w];
+        const int n2 = ng * N / 2;
+        WordWalk wk = walk_start(tid, hl);
+#pragma unroll 4
+        for (int w = tid; w < n2; w += nt) {
+            const u32x4 v = src[w];
+            const int q = wk.row + 2 * wk.xh;
+            lat[q] = ((uint64_t)v.y << 32) | v.x;
+            lat[q + 1] = ((uint64_t)v.w << 32) | v.z;
+            walk_advance(wk, step);
+        }
     } else {
+        // one site (64 bytes, four 16-byte loads) per thread and step
         const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes));
-        uint16_t *l16 = reinterpret_cast<uint16_t *>(lat);
-        const int n16 = ng * N * 4;
-#pragma unroll 8
-        for (int it = tid; it < n16; it += nt) {
-            const u32x4 v = src[it];
-            l16[it] = (uint16_t)pack16(uint4{v.x, v.y, v.z, v.w});
+        const WalkStep sstep = walk_step(nt, hl, L);
+        WordWalk wk = walk_start(tid, hl, L);
+#pragma unroll 2
+        for (int e = tid; e < ng * N; e += nt) {
+            uint64_t w = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const u32x4 v = src[4 * e + k];
+                w |= (uint64_t)pack16(uint4{v.x, v.y, v.z, v.w}) << (16 * k);
+            }
+            lat[wk.row + wk.xh] = w;
+            walk_advance(wk, sstep);
         }
     }
+    const HaloItem mine = tid < ng * 4 * L ? halo_item(hl, tid) : HaloItem{-1, -1};
     for (int k = tid; k < ng * kLanes; k += nt) {
         red_u[k] = 0;
         red_up[k] = 0;
     }
+    __syncthreads();
+    fill_halo(lat, hl, ng, mine);
     __syncthreads();
 
     const int theta = init ? 0 : rd.theta;
     const int i = st->step + 1;
     const uint64_t t4 = st->t4, t8 = st->t8;
     const bool all4 = t4 >= (1ull << 32), all8 = t8 >= (1ull << 32);
-    // threshold bits are the same for every lane: keep them in scalar registers
-    const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
-    const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
-    const float inv_half = 1.0f / (float)half, inv_L = 1.0f / (float)L;
     const int words = ng * (N >> 1);  // sites of one colour, all groups of the block
     const uint64_t last_valid = lane_mask(Rn - (g0 + ng - 1) * kLanes);
-    const WalkStep step = walk_step(nt, half, L);
-    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-    // per-wavefront lists of undecided words (two, used alternately): word
-    // index and the mask of still undecided lanes
-    const int cap = cpl * kLanes;
-    uint64_t *und_list = lat + (size_t)gpb * N + (size_t)wave * 2 * cap;
-    uint16_t *idx_list = reinterpret_cast<uint16_t *>(lat + (size_t)gpb * N + (size_t)nw * 2 * cap) +
-                         (size_t)wave * 2 * cap;
+    const int P = hl.P;
     const uint32_t k0 = rd.key0, k1 = rd.key1;
     uint32_t calls = 0;
     for (int s = 0; s < theta; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
-            if (!POOLED) {
-                // lane-local: each word's comparison runs to the end in its lane;
-                // the thread walks the words tid, tid + nt, ... incrementally
-                WordWalk wk = walk_start(tid, half, L);
-                for (int idx = tid; idx < words; idx += nt) {
-                    const int x = 2 * wk.xh + ((colour + wk.y) & 1);
-                    const int site = wk.row + x;
-                    const int rgt = (x == L - 1) ? wk.row : site + 1;
-                    const int lft = (x == 0) ? site + L - 1 : site - 1;
-                    const int up = (wk.y == 0) ? site + N - L : site - L;
-                    const int dn = (wk.y == L - 1) ? site + L - N : site + L;
-                    const uint64_t s0 = lat[site];
-                    const uint64_t valid = wk.gl == ng - 1 ? last_valid : ~0ull;
-                    const uint64_t f = metropolis_word(s0 ^ lat[rgt], s0 ^ lat[lft], s0 ^ lat[up],
-                                                       s0 ^ lat[dn], valid, t4, t8, all4, all8, k0,
-                                                       k1, (uint32_t)(wk.y * half + wk.xh),
-                                                       (uint32_t)(g0 + wk.gl), h, &calls);
-                    lat[site] = s0 ^ f;
-                    walk_advance(wk, step);
-                }
-                __syncthreads();
-                continue;
+            WordWalk wk = walk_start(tid, hl);
+            for (int idx = tid; idx < words; idx += nt) {
+                const int x = 2 * wk.xh + ((colour + wk.y) & 1);
+                const int site = wk.row + x;
+                const uint64_t s0 = lat[site];
+                const uint64_t valid = wk.gl == ng - 1 ? last_valid : ~0ull;
+                const uint64_t f = metropolis_word(s0 ^ lat[site + 1], s0 ^ lat[site - 1],
+                                                   s0 ^ lat[site - P], s0 ^ lat[site + P], valid, t4,
+                                                   t8, all4, all8, k0, k1,
+                                                   (uint32_t)(wk.y * half + wk.xh),
+                                                   (uint32_t)(g0 + wk.gl), h, &calls);
+                lat[site] = s0 ^ f;
+                walk_advance(wk, step);
             }
-            for (int b0 = 0; b0 < words; b0 += cpl * nt) {
-                // phase A: each lane takes cpl words and spends up to kPlanePairs
-                // Philox calls on each; still undecided words go to the list
-                int cnt = 0;
-                for (int k = 0; k < cpl; ++k) {
-                    const int idx = b0 + wave * cap + k * kLanes + lane;
-                    const bool active = idx < words;
-                    uint64_t und = 0;
-                    if (active) {
-                        const WordPos w = word_pos(idx, colour, L, N, half, inv_half, inv_L);
-                        const int g = g0 + w.gl;
-                        const uint64_t valid = lane_mask(Rn - g * kLanes);
-                        const uint64_t s0 = lat[w.site];
-                        WordClass c = classify(s0 ^ lat[w.r], s0 ^ lat[w.l], s0 ^ lat[w.u], s0 ^ lat[w.d]);
-                        uint64_t flip = c.ge2;
-                        if (all4) { flip |= c.eq1; c.eq1 = 0; }
-                        if (all8) { flip |= c.eq0; c.eq0 = 0; }
-                        flip &= valid;
-                        c.eq1 &= valid;
-                        und = (c.eq1 | c.eq0) & valid;
-#pragma unroll
-                        for (uint32_t p = 0; p < kPlanePairs; ++p) {
-                            if (und) {
-                                const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagSweep | p);
-                                Lanes s{(uint32_t)und, (uint32_t)(und >> 32), (uint32_t)flip,
-                                        (uint32_t)(flip >> 32)};
-                                plane_pair(s, (uint32_t)c.eq1, (uint32_t)(c.eq1 >> 32), T4, T8, p, x);
-                                und = ((uint64_t)s.uh << 32) | s.ul;
-                                flip = ((uint64_t)s.fh << 32) | s.fl;
-                                ++calls;
-                            }
-                        }
-                        lat[w.site] = s0 ^ flip;
-                    }
-                    const bool pend = active && und != 0;
-                    const uint64_t m = __ballot(pend);
-                    if (pend) {
-                        const int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
-                        idx_list[pos] = (uint16_t)idx;
-                        und_list[pos] = und;
-                    }
-                    cnt += __popcll(m);
-                }
-                // phase B: one tie call per round for every listed word, all
-                // lanes of the wavefront working on the list
-                int cur = 0;
-                for (uint32_t q = 0; cnt > 0; ++q) {
-                    int next = 0;
-                    for (int base = 0; base < cnt; base += kLanes) {
-                        const int e = base + lane;
-                        const bool act = e < cnt;
-                        uint64_t und = 0;
-                        int idx = 0;
-                        if (act) {
-                            idx = idx_list[cur * cap + e];
-                            und = und_list[cur * cap + e];
-                            const WordPos w = word_pos(idx, colour, L, N, half, inv_half, inv_L);
-                            const int g = g0 + w.gl;
-                            // undecided lanes still hold their original spin, so
-                            // their classes can be recomputed from the lattice
-                            const uint64_t s0 = lat[w.site];
-                            const WordClass c = classify(s0 ^ lat[w.r], s0 ^ lat[w.l], s0 ^ lat[w.u],
-                                                         s0 ^ lat[w.d]);
-                            const U4 x = philox(k0, k1, (uint32_t)w.wi, (uint32_t)g, h, kTagTie | q);
-                            uint64_t acc = 0;
-                            tie_call(und, c.eq1, T4 & kLow26, T8 & kLow26, x, acc);
-                            ++calls;
-                            if (acc) lat[w.site] = s0 ^ acc;
-                        }
-                        const bool pend = act && und != 0;
-                        const uint64_t m = __ballot(pend);
-                        if (pend) {
-                            const int pos = next + __popcll(m & ((1ull << lane) - 1ull));
-                            idx_list[(cur ^ 1) * cap + pos] = (uint16_t)idx;
-                            und_list[(cur ^ 1) * cap + pos] = und;
-                        }
-                        next += __popcll(m);
-                    }
-                    cur ^= 1;
-                    cnt = next;
-                }
-            }
+            __syncthreads();
+            fill_halo(lat, hl, ng, mine);
             __syncthreads();
         }
     }
@@ -1198,18 +1114,15 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         const int lane = tid & 63;
         const int dy = nt / L, dx = nt - dy * L;
         for (int gl = 0; gl < ng; ++gl) {
-            const int base = gl * N;
             int y = tid / L, x = tid - (tid / L) * L;
             for (int c0 = 0; c0 < N; c0 += kMeasSites * nt) {  // same trip count in every thread
                 MeasCounters mc;
 #pragma unroll
                 for (int j = 0; j < kMeasSites; ++j) {
                     if (c0 + j * nt + tid < N) {
-                        const int row = base + y * L;
-                        const uint64_t w0 = lat[row + x];
-                        const uint64_t wr = lat[row + ((x == L - 1) ? 0 : x + 1)];
-                        const uint64_t wd = lat[((y == L - 1) ? base : row + L) + x];
-                        mc.add(w0 ^ wr, w0 ^ wd, w0);
+                        const int q = hl.at(gl, x, y);
+                        const uint64_t w0 = lat[q];
+                        mc.add(w0 ^ lat[q + 1], w0 ^ lat[q + P], w0);
                     }
                     x += dx;
                     y += dy;
@@ -1242,14 +1155,25 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     if (theta > 0) {
         if (LAYOUT == PA_LAYOUT_MSC64) {
             const gptr<u32x4> dst = global(reinterpret_cast<u32x4 *>(rd.ms[nb] + (size_t)g0 * N));
-            const u32x4 *l2 = reinterpret_cast<const u32x4 *>(lat);
-            for (int w = tid; w < ng * N / 2; w += nt) dst[w] = l2[w];
+            WordWalk wk = walk_start(tid, hl);
+            for (int w = tid; w < ng * N / 2; w += nt) {
+                const int q = wk.row + 2 * wk.xh;
+                const uint64_t a = lat[q], b = lat[q + 1];
+                dst[w] = u32x4{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+                walk_advance(wk, step);
+            }
         } else {
             const gptr<u32x4> dst = global(reinterpret_cast<u32x4 *>(rd.s8[nb] + (size_t)g0 * N * kLanes));
-            const uint16_t *l16 = reinterpret_cast<const uint16_t *>(lat);
-            for (int it = tid; it < ng * N * 4; it += nt) {
-                const uint4 v = unpack16(l16[it]);
-                dst[it] = u32x4{v.x, v.y, v.z, v.w};
+            const WalkStep sstep = walk_step(nt, hl, L);
+            WordWalk wk = walk_start(tid, hl, L);
+            for (int e = tid; e < ng * N; e += nt) {
+                const uint64_t w = lat[wk.row + wk.xh];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint4 v = unpack16((uint32_t)(w >> (16 * k)) & 0xFFFFu);
+                    dst[4 * e + k] = u32x4{v.x, v.y, v.z, v.w};
+                }
+                walk_advance(wk, sstep);
             }
         }
     }
@@ -1548,37 +1472,18 @@ hipError_t launch_init(const LaunchCtx &c) {
     return hipSuccess;
 }
 
-size_t sweep_lds_bytes(int N, int gpb, int threads, int cpl) {
-    return (size_t)gpb * N * 8 + (size_t)(threads / 64) * 2 * cpl * kLanes * (8 + 2);
-}
-
-// words per lane per batch: as many as the LDS left beside the lattices allows (<= 4)
-int sweep_cpl(int N, int gpb, int threads) {
-    for (int cpl = 4; cpl > 1; --cpl)
-        if (sweep_lds_bytes(N, gpb, threads, cpl) <= (size_t)kMaxSweepLds) return cpl;
-    return 1;
-}
+// LDS of one sweep block: gpb lattices with their halo
+size_t sweep_lds_bytes(int L, int gpb) { return (size_t)gpb * (L + 2) * (L + 2) * 8; }
 
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
     for (const auto &cls : c.sweep_classes) {
-        const int cpl = cls.pooled ? sweep_cpl(cls.N, cls.gpb, cls.threads) : 0;
-        const size_t lds = sweep_lds_bytes(cls.N, cls.gpb, cls.threads, cpl);
-        if (cls.has_msc) {
-            if (cls.pooled)
-                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, 1>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
-            else
-                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, 0>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
-        }
-        if (cls.has_int8) {
-            if (cls.pooled)
-                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, 1>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
-            else
-                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, 0>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb, cpl);
-        }
+        const size_t lds = sweep_lds_bytes(cls.L, cls.gpb);
+        if (cls.has_msc)
+            PA_LAUNCH(k_sweep<PA_LAYOUT_MSC64>, dim3(cls.total), dim3(cls.threads), lds, c.stream,
+                      c.runs, cls.map, init, cls.gpb);
+        if (cls.has_int8)
+            PA_LAUNCH(k_sweep<PA_LAYOUT_INT8>, dim3(cls.total), dim3(cls.threads), lds, c.stream,
+                      c.runs, cls.map, init, cls.gpb);
     }
     return hipSuccess;
 }
@@ -1675,8 +1580,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 
 hipError_t configure_kernels() {
     // up to kMaxSweepLds bytes of lattice (+ word lists) per block
-    const void *fns[4] = {(const void *)k_sweep<PA_LAYOUT_MSC64, 0>, (const void *)k_sweep<PA_LAYOUT_MSC64, 1>,
-                          (const void *)k_sweep<PA_LAYOUT_INT8, 0>, (const void *)k_sweep<PA_LAYOUT_INT8, 1>};
+    const void *fns[2] = {(const void *)k_sweep<PA_LAYOUT_MSC64>, (const void *)k_sweep<PA_LAYOUT_INT8>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
         if (e != hipSuccess) return e;

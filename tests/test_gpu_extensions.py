@@ -222,17 +222,24 @@ def test_learned_schedule_runs_and_logs():
     run.close()
 
 
-def test_sweep_geometry_does_not_change_results():
+@pytest.mark.parametrize("L", [16, 6])
+def test_sweep_geometry_does_not_change_results(L):
+    # L = 6: the thread stride is not a multiple of a row, so the word walk
+    # carries across rows and groups
     betas = linear_schedule(0.5, 4)
     states = []
-    for threads, gpb, variant in ((256, 4, 0), (64, 1, 1), (1024, 2, 0), (128, 8, 1), (512, 1, 1)):
-        r = pa.Run(16, 1000, betas, 3, 61, "nearest", "msc64")
-        r.set_sweep_launch(16, threads, gpb, variant)
-        assert r.sweep_launch(16) == (threads, gpb, variant)
+    for threads, gpb in ((256, 4), (64, 1), (1024, 2), (128, 8), (512, 1), (192, 3)):
+        r = pa.Run(L, 1000, betas, 3, 61, "nearest", "msc64")
+        r.set_sweep_launch(L, threads, gpb)
+        assert r.sweep_launch(L) == (threads, gpb, 0)
         r.run(4)
         states.append(r.get_state())
         r.close()
     assert all(s == states[0] for s in states)
+    r = pa.Run(L, 64, betas, 3, 61, "nearest", "msc64")
+    with pytest.raises(pa.PAError):
+        r.set_sweep_launch(L, 256, 1, 1)  # only variant 0 exists
+    r.close()
 
 
 def test_autotuner_times_candidates_and_keeps_results():
