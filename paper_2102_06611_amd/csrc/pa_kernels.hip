@@ -931,6 +931,18 @@ __device__ __forceinline__ void walk_advance(WordWalk &w, const WalkStep &s) {
     }
 }
 
+// walk_advance when the stride is a whole number of rows (dxh == 0)
+__device__ __forceinline__ void walk_advance_rows(WordWalk &w, const WalkStep &s) {
+    w.row += s.drow;
+    w.y += s.dy;
+    w.gl += s.dgl;
+    if (w.y >= s.L) {
+        w.y -= s.L;
+        w.gl += 1;
+        w.row += s.wrap;
+    }
+}
+
 // Bit-sliced counters for the measurement: plane k holds bit k of the 64
 // replicas' counts (one 32-bit half per array).  add() takes the two bond
 // bits and the spin bit of one site word: a full adder puts the two bond bits
@@ -1015,7 +1027,7 @@ struct MeasCounters {
 // bonds) and M are measured.  With init != 0 no sweep is done.
 constexpr int kMaxGroupsPerBlock = 8;
 
-template <int LAYOUT>
+template <int LAYOUT, bool ROWS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     extern __shared__ uint64_t lat[];
@@ -1098,7 +1110,10 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
                                                    (uint32_t)(wk.y * half + wk.xh),
                                                    (uint32_t)(g0 + wk.gl), h, &calls);
                 lat[site] = s0 ^ f;
-                walk_advance(wk, step);
+                if (ROWS)
+                    walk_advance_rows(wk, step);
+                else
+                    walk_advance(wk, step);
             }
             __syncthreads();
             fill_halo(lat, hl, ng, mine);
@@ -1478,12 +1493,23 @@ size_t sweep_lds_bytes(int L, int gpb) { return (size_t)gpb * (L + 2) * (L + 2) 
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
     for (const auto &cls : c.sweep_classes) {
         const size_t lds = sweep_lds_bytes(cls.L, cls.gpb);
-        if (cls.has_msc)
-            PA_LAUNCH(k_sweep<PA_LAYOUT_MSC64>, dim3(cls.total), dim3(cls.threads), lds, c.stream,
-                      c.runs, cls.map, init, cls.gpb);
-        if (cls.has_int8)
-            PA_LAUNCH(k_sweep<PA_LAYOUT_INT8>, dim3(cls.total), dim3(cls.threads), lds, c.stream,
-                      c.runs, cls.map, init, cls.gpb);
+        const bool rows = cls.threads % (cls.L / 2) == 0;  // the word walk moves whole rows
+        if (cls.has_msc) {
+            if (rows)
+                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, true>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb);
+            else
+                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, false>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb);
+        }
+        if (cls.has_int8) {
+            if (rows)
+                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, true>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb);
+            else
+                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, false>), dim3(cls.total), dim3(cls.threads), lds,
+                          c.stream, c.runs, cls.map, init, cls.gpb);
+        }
     }
     return hipSuccess;
 }
@@ -1580,7 +1606,8 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 
 hipError_t configure_kernels() {
     // up to kMaxSweepLds bytes of lattice (+ word lists) per block
-    const void *fns[2] = {(const void *)k_sweep<PA_LAYOUT_MSC64>, (const void *)k_sweep<PA_LAYOUT_INT8>};
+    const void *fns[4] = {(const void *)k_sweep<PA_LAYOUT_MSC64, true>, (const void *)k_sweep<PA_LAYOUT_MSC64, false>,
+                          (const void *)k_sweep<PA_LAYOUT_INT8, true>, (const void *)k_sweep<PA_LAYOUT_INT8, false>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
         if (e != hipSuccess) return e;
