@@ -662,6 +662,51 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
 #pragma unroll
         for (int m = 0; m < 4; ++m) pc[m] = __shfl(p, 4 * k + m, 64);
         const uint8_t *st8 = reinterpret_cast<const uint8_t *>(stage);
+        constexpr int kPass = kGatherSites * 4;  // 16-byte elements per parent group and pass
+        if (g_last - g_first < kGatherPg) {
+            // all parent groups fit one pass: the next pass's rows are loaded
+            // into registers while the current one is picked from LDS
+            const int ngb = g_last - g_first + 1;
+            u32x4 pre[kGatherPg];
+            auto load = [&](int s0) {
+#pragma unroll
+                for (int b = 0; b < kGatherPg; ++b) {
+                    const int srow = s0 + ((int)threadIdx.x >> 2);
+                    if (b < ngb && srow < N)
+                        pre[b] = src[((size_t)(g_first + b) * N + srow) * 4 + (threadIdx.x & 3)];
+                }
+            };
+            load(0);
+            for (int s0 = 0; s0 < N; s0 += kGatherSites) {
+                __syncthreads();  // the previous pass's readers are done
+#pragma unroll
+                for (int b = 0; b < kGatherPg; ++b)
+                    if (b < ngb) stage[b * kPass + threadIdx.x] = pre[b];
+                __syncthreads();
+                if (s0 + kGatherSites < N) load(s0 + kGatherSites);
+                uint32_t out[kGatherSites / 16];
+#pragma unroll
+                for (int r = 0; r < kGatherSites / 16; ++r) {
+                    out[r] = 0;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        if (pc[m] < 0) {
+                            out[r] |= 0xFFu << (8 * m);  // past the population: spin -1
+                        } else {
+                            const uint8_t *row = st8 + ((pc[m] >> 6) - g_first) * (kGatherSites * 64) +
+                                                 (pc[m] & 63);
+                            out[r] |= (uint32_t)row[(sl + 16 * r) * 64] << (8 * m);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kGatherSites / 16; ++r) {
+                    const int site = s0 + sl + 16 * r;
+                    if (site < N) dst[(size_t)site * 16 + k] = out[r];
+                }
+            }
+            return;
+        }
         for (int s0 = 0; s0 < N; s0 += kGatherSites) {
             uint32_t out[kGatherSites / 16];
 #pragma unroll
@@ -675,8 +720,8 @@ __global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map
                 const int ngb = min(kGatherPg, g_last - gb + 1);
                 __syncthreads();  // the previous pass's readers are done
                 // ngb groups x kGatherSites rows x 4 uint4, spread over the block
-                for (int e = threadIdx.x; e < ngb * kGatherSites * 4; e += blockDim.x) {
-                    const int b = e / (kGatherSites * 4), r = e - b * (kGatherSites * 4);
+                for (int e = threadIdx.x; e < ngb * kPass; e += blockDim.x) {
+                    const int b = e / kPass, r = e - b * kPass;
                     const int srow = s0 + (r >> 2);
                     if (srow < N) stage[e] = src[((size_t)(gb + b) * N + srow) * 4 + (r & 3)];
                 }
