@@ -806,36 +806,42 @@ __device__ __forceinline__ void plane_half(uint32_t &und, uint32_t &flip, uint32
 struct Lanes {
     uint32_t ul, uh, fl, fh;  // undecided and accepted lanes, low and high halves
 };
-template <int C>
-__device__ __forceinline__ void plane_pair_case(Lanes &s, uint32_t el, uint32_t eh, const U4 &x) {
+template <int C, int K>
+__device__ __forceinline__ void plane_pair_case(Lanes *s, const uint32_t *el, const uint32_t *eh,
+                                                const U4 *x) {
     constexpr int A4 = (C >> 3) & 1, A8 = (C >> 2) & 1, B4 = (C >> 1) & 1, B8 = C & 1;
-    plane_half<A4, A8>(s.ul, s.fl, el, x.x);
-    plane_half<A4, A8>(s.uh, s.fh, eh, x.y);
-    plane_half<B4, B8>(s.ul, s.fl, el, x.z);
-    plane_half<B4, B8>(s.uh, s.fh, eh, x.w);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        plane_half<A4, A8>(s[k].ul, s[k].fl, el[k], x[k].x);
+        plane_half<A4, A8>(s[k].uh, s[k].fh, eh[k], x[k].y);
+        plane_half<B4, B8>(s[k].ul, s[k].fl, el[k], x[k].z);
+        plane_half<B4, B8>(s[k].uh, s[k].fh, eh[k], x[k].w);
+    }
 }
-__device__ __forceinline__ void plane_pair(Lanes &s, uint32_t el, uint32_t eh, uint32_t T4,
-                                           uint32_t T8, uint32_t p, const U4 &x) {
+// K words at once (their threshold bits are the same)
+template <int K>
+__device__ __forceinline__ void plane_pair(Lanes *s, const uint32_t *el, const uint32_t *eh,
+                                           uint32_t T4, uint32_t T8, uint32_t p, const U4 *x) {
     const uint32_t sa = 31u - 2u * p, sb = 30u - 2u * p;
     const uint32_t c = (((T4 >> sa) & 1u) << 3) | (((T8 >> sa) & 1u) << 2) |
                        (((T4 >> sb) & 1u) << 1) | ((T8 >> sb) & 1u);
     switch (c) {
-    case 0: plane_pair_case<0>(s, el, eh, x); break;
-    case 1: plane_pair_case<1>(s, el, eh, x); break;
-    case 2: plane_pair_case<2>(s, el, eh, x); break;
-    case 3: plane_pair_case<3>(s, el, eh, x); break;
-    case 4: plane_pair_case<4>(s, el, eh, x); break;
-    case 5: plane_pair_case<5>(s, el, eh, x); break;
-    case 6: plane_pair_case<6>(s, el, eh, x); break;
-    case 7: plane_pair_case<7>(s, el, eh, x); break;
-    case 8: plane_pair_case<8>(s, el, eh, x); break;
-    case 9: plane_pair_case<9>(s, el, eh, x); break;
-    case 10: plane_pair_case<10>(s, el, eh, x); break;
-    case 11: plane_pair_case<11>(s, el, eh, x); break;
-    case 12: plane_pair_case<12>(s, el, eh, x); break;
-    case 13: plane_pair_case<13>(s, el, eh, x); break;
-    case 14: plane_pair_case<14>(s, el, eh, x); break;
-    default: plane_pair_case<15>(s, el, eh, x); break;
+    case 0: plane_pair_case<0, K>(s, el, eh, x); break;
+    case 1: plane_pair_case<1, K>(s, el, eh, x); break;
+    case 2: plane_pair_case<2, K>(s, el, eh, x); break;
+    case 3: plane_pair_case<3, K>(s, el, eh, x); break;
+    case 4: plane_pair_case<4, K>(s, el, eh, x); break;
+    case 5: plane_pair_case<5, K>(s, el, eh, x); break;
+    case 6: plane_pair_case<6, K>(s, el, eh, x); break;
+    case 7: plane_pair_case<7, K>(s, el, eh, x); break;
+    case 8: plane_pair_case<8, K>(s, el, eh, x); break;
+    case 9: plane_pair_case<9, K>(s, el, eh, x); break;
+    case 10: plane_pair_case<10, K>(s, el, eh, x); break;
+    case 11: plane_pair_case<11, K>(s, el, eh, x); break;
+    case 12: plane_pair_case<12, K>(s, el, eh, x); break;
+    case 13: plane_pair_case<13, K>(s, el, eh, x); break;
+    case 14: plane_pair_case<14, K>(s, el, eh, x); break;
+    default: plane_pair_case<15, K>(s, el, eh, x); break;
     }
 }
 
@@ -863,7 +869,7 @@ __device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t L
     tie_one(und, eq1, L4, L8, x.w, flip);
 }
 
-// Lane-local variant: the whole comparison of one word in its own lane.  With
+// The whole comparison of one word (64 replicas of one site) in one lane.  With
 // a_k = s XOR n_k (antiparallel neighbours), A = sum a_k and dE = 8 - 4A:
 // A >= 2 (dE <= 0) always flips; A = 1 (dE = 4) and A = 0 (dE = 8) flip iff
 // u32 < t4 / t8.  The top six bits of u32 are compared bit plane by bit plane
@@ -893,7 +899,7 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     uint32_t p = 0;
     for (; (s.ul | s.uh) != 0 && p < kPlanePairs; ++p) {
         const U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
-        plane_pair(s, el, eh, T4, T8, p, x);
+        plane_pair<1>(&s, &el, &eh, T4, T8, p, &x);
     }
     und = ((uint64_t)s.uh << 32) | s.ul;
     flip = ((uint64_t)s.fh << 32) | s.fl;
@@ -904,6 +910,74 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     }
     *calls += p + q;
     return flip;
+}
+
+// The same comparison for K words in one lane at once: their Philox chains
+// are independent instruction streams (for launches too large for more than
+// one block per CU, where few wavefronts share a SIMD).
+// In: nb[k][0..3] the neighbour words and s0[k] the site word; out: flip[k].
+template <int K>
+__device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const uint64_t *s0,
+                                                 const uint64_t *valid, uint64_t t4, uint64_t t8,
+                                                 bool all4, bool all8, uint32_t k0, uint32_t k1,
+                                                 const uint32_t *w, const uint32_t *g, uint32_t h,
+                                                 uint64_t *flip, uint32_t *calls) {
+    Lanes s[K];
+    uint32_t el[K], eh[K];
+    uint64_t eq1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const WordClass2 c = classes(s0[k] ^ nbr[k][0], s0[k] ^ nbr[k][1], s0[k] ^ nbr[k][2],
+                                     s0[k] ^ nbr[k][3]);
+        eq1[k] = c.eq1;
+        uint64_t f = c.ge2 & valid[k];
+        uint64_t und = valid[k] & ~c.ge2;
+        if (all4 || all8) {  // beta <= 0: a threshold of 2^32 accepts its whole class
+            const uint64_t e1 = und & c.eq1, e0 = und & ~c.eq1;
+            if (all4) { f |= e1; und &= ~e1; }
+            if (all8) { f |= e0; und &= ~e0; }
+        }
+        s[k] = Lanes{(uint32_t)und, (uint32_t)(und >> 32), (uint32_t)f, (uint32_t)(f >> 32)};
+        el[k] = (uint32_t)c.eq1;
+        eh[k] = (uint32_t)(c.eq1 >> 32);
+    }
+    // the thresholds are the same for every lane: keep their bits in scalar registers
+    const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
+    const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
+    for (uint32_t p = 0; p < kPlanePairs; ++p) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool open = (s[k].ul | s[k].uh) != 0;
+            any |= open;
+            *calls += open ? 1u : 0u;
+        }
+        if (!any) break;
+        U4 x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = philox(k0, k1, w[k], g[k], h, kTagSweep | p);
+        plane_pair<K>(s, el, eh, T4, T8, p, x);
+    }
+    uint64_t und[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        und[k] = ((uint64_t)s[k].uh << 32) | s[k].ul;
+        flip[k] = ((uint64_t)s[k].fh << 32) | s[k].fl;
+    }
+    for (uint32_t q = 0;; ++q) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            any |= und[k] != 0;
+            *calls += und[k] != 0 ? 1u : 0u;
+        }
+        if (!any) break;
+        U4 x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = philox(k0, k1, w[k], g[k], h, kTagTie | q);
+#pragma unroll
+        for (int k = 0; k < K; ++k) tie_call(und[k], eq1[k], T4 & kLow26, T8 & kLow26, x[k], flip[k]);
+    }
 }
 
 // The block's lattices in LDS carry a halo: group gl's site (x, y) is word
@@ -1072,8 +1146,8 @@ struct MeasCounters {
 // bonds) and M are measured.  With init != 0 no sweep is done.
 constexpr int kMaxGroupsPerBlock = 8;
 
-template <int LAYOUT, bool ROWS>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+template <int LAYOUT, bool ROWS, int ILP>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ILP == 1 ? 8 : 4)))
 k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     extern __shared__ uint64_t lat[];
     __shared__ int32_t red_u[kMaxGroupsPerBlock * kLanes], red_up[kMaxGroupsPerBlock * kLanes];
@@ -1144,21 +1218,54 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
         for (int colour = 0; colour < 2; ++colour) {
             const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
             WordWalk wk = walk_start(tid, hl);
-            for (int idx = tid; idx < words; idx += nt) {
-                const int x = 2 * wk.xh + ((colour + wk.y) & 1);
-                const int site = wk.row + x;
-                const uint64_t s0 = lat[site];
-                const uint64_t valid = wk.gl == ng - 1 ? last_valid : ~0ull;
-                const uint64_t f = metropolis_word(s0 ^ lat[site + 1], s0 ^ lat[site - 1],
-                                                   s0 ^ lat[site - P], s0 ^ lat[site + P], valid, t4,
-                                                   t8, all4, all8, k0, k1,
-                                                   (uint32_t)(wk.y * half + wk.xh),
-                                                   (uint32_t)(g0 + wk.gl), h, &calls);
-                lat[site] = s0 ^ f;
-                if (ROWS)
-                    walk_advance_rows(wk, step);
-                else
-                    walk_advance(wk, step);
+            if (ILP == 1) {
+                for (int idx = tid; idx < words; idx += nt) {
+                    const int x = 2 * wk.xh + ((colour + wk.y) & 1);
+                    const int site = wk.row + x;
+                    const uint64_t s0 = lat[site];
+                    const uint64_t valid = wk.gl == ng - 1 ? last_valid : ~0ull;
+                    const uint64_t f = metropolis_word(s0 ^ lat[site + 1], s0 ^ lat[site - 1],
+                                                       s0 ^ lat[site - P], s0 ^ lat[site + P], valid,
+                                                       t4, t8, all4, all8, k0, k1,
+                                                       (uint32_t)(wk.y * half + wk.xh),
+                                                       (uint32_t)(g0 + wk.gl), h, &calls);
+                    lat[site] = s0 ^ f;
+                    if (ROWS)
+                        walk_advance_rows(wk, step);
+                    else
+                        walk_advance(wk, step);
+                }
+            } else {
+                // the thread's words idx, idx + nt, ... taken ILP at a time
+                for (int idx = tid; idx < words; idx += ILP * nt) {
+                    int site[ILP];
+                    uint64_t s0[ILP], nbr[ILP][4], valid[ILP], f[ILP];
+                    uint32_t wi[ILP], gi[ILP];
+#pragma unroll
+                    for (int k = 0; k < ILP; ++k) {
+                        const bool live = k == 0 || idx + k * nt < words;
+                        const int x = 2 * wk.xh + ((colour + wk.y) & 1);
+                        site[k] = wk.row + x;
+                        if (!live) site[k] = site[0];  // past the last word: a dummy with no lanes
+                        s0[k] = lat[site[k]];
+                        nbr[k][0] = lat[site[k] + 1];
+                        nbr[k][1] = lat[site[k] - 1];
+                        nbr[k][2] = lat[site[k] - P];
+                        nbr[k][3] = lat[site[k] + P];
+                        valid[k] = !live ? 0ull : (wk.gl == ng - 1 ? last_valid : ~0ull);
+                        wi[k] = (uint32_t)(wk.y * half + wk.xh);
+                        gi[k] = (uint32_t)(g0 + wk.gl);
+                        if (ROWS)
+                            walk_advance_rows(wk, step);
+                        else
+                            walk_advance(wk, step);
+                    }
+                    metropolis_words<ILP>(nbr, s0, valid, t4, t8, all4, all8, k0, k1, wi, gi, h, f,
+                                          &calls);
+#pragma unroll
+                    for (int k = 0; k < ILP; ++k)
+                        if (f[k]) lat[site[k]] = s0[k] ^ f[k];
+                }
             }
             __syncthreads();
             fill_halo(lat, hl, ng, mine);
@@ -1535,25 +1642,29 @@ hipError_t launch_init(const LaunchCtx &c) {
 // LDS of one sweep block: gpb lattices with their halo
 size_t sweep_lds_bytes(int L, int gpb) { return (size_t)gpb * (L + 2) * (L + 2) * 8; }
 
+// k_sweep instantiation for a layout and sel = rows (bit 0) | two words per thread (bit 1)
+static const void *sweep_kernel(int layout, int sel) {
+    static const void *const fns[2][4] = {
+        {(const void *)k_sweep<0, false, 1>, (const void *)k_sweep<0, true, 1>,
+         (const void *)k_sweep<0, false, 2>, (const void *)k_sweep<0, true, 2>},
+        {(const void *)k_sweep<1, false, 1>, (const void *)k_sweep<1, true, 1>,
+         (const void *)k_sweep<1, false, 2>, (const void *)k_sweep<1, true, 2>}};
+    return fns[layout][sel];
+}
+
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
     for (const auto &cls : c.sweep_classes) {
         const size_t lds = sweep_lds_bytes(cls.L, cls.gpb);
         const bool rows = cls.threads % (cls.L / 2) == 0;  // the word walk moves whole rows
-        if (cls.has_msc) {
-            if (rows)
-                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, true>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb);
-            else
-                PA_LAUNCH((k_sweep<PA_LAYOUT_MSC64, false>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb);
-        }
-        if (cls.has_int8) {
-            if (rows)
-                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, true>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb);
-            else
-                PA_LAUNCH((k_sweep<PA_LAYOUT_INT8, false>), dim3(cls.total), dim3(cls.threads), lds,
-                          c.stream, c.runs, cls.map, init, cls.gpb);
+        // a block that fills a CU's LDS runs alone: two words per thread at once
+        const bool ilp = lds > kMaxSweepLds / 2;
+        const int sel = (rows ? 1 : 0) | (ilp ? 2 : 0);
+        for (int layout = 0; layout < 2; ++layout) {
+            if (!(layout == PA_LAYOUT_MSC64 ? cls.has_msc : cls.has_int8)) continue;
+            const void *fn = sweep_kernel(layout, sel);
+            void *args[] = {(void *)&c.runs, (void *)&cls.map, (void *)&init, (void *)&cls.gpb};
+            hipError_t e = hipLaunchKernel(fn, dim3(cls.total), dim3(cls.threads), args, lds, c.stream);
+            if (e != hipSuccess) return e;
         }
     }
     return hipSuccess;
@@ -1650,10 +1761,9 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 }
 
 hipError_t configure_kernels() {
-    // up to kMaxSweepLds bytes of lattice (+ word lists) per block
-    const void *fns[4] = {(const void *)k_sweep<PA_LAYOUT_MSC64, true>, (const void *)k_sweep<PA_LAYOUT_MSC64, false>,
-                          (const void *)k_sweep<PA_LAYOUT_INT8, true>, (const void *)k_sweep<PA_LAYOUT_INT8, false>};
-    for (const void *f : fns) {
+    // up to kMaxSweepLds bytes of lattices (with their halo) per sweep block
+    for (int k = 0; k < 8; ++k) {
+        const void *f = sweep_kernel(k >> 2, k & 3);
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
         if (e != hipSuccess) return e;
     }

@@ -222,13 +222,21 @@ def test_learned_schedule_runs_and_logs():
     run.close()
 
 
-@pytest.mark.parametrize("L", [16, 6])
+GEOMETRIES = {
+    16: ((256, 4), (64, 1), (1024, 2), (128, 8), (512, 1), (192, 3)),
+    # the thread stride is not a multiple of a row: the word walk carries
+    # across rows and groups
+    6: ((256, 4), (64, 1), (1024, 2), (128, 8), (512, 1), (192, 3)),
+    # three or four groups fill more than half the LDS: two words per thread
+    64: ((512, 1), (256, 3), (1024, 4), (320, 3)),
+}
+
+
+@pytest.mark.parametrize("L", sorted(GEOMETRIES))
 def test_sweep_geometry_does_not_change_results(L):
-    # L = 6: the thread stride is not a multiple of a row, so the word walk
-    # carries across rows and groups
     betas = linear_schedule(0.5, 4)
     states = []
-    for threads, gpb in ((256, 4), (64, 1), (1024, 2), (128, 8), (512, 1), (192, 3)):
+    for threads, gpb in GEOMETRIES[L]:
         r = pa.Run(L, 1000, betas, 3, 61, "nearest", "msc64")
         r.set_sweep_launch(L, threads, gpb)
         assert r.sweep_launch(L) == (threads, gpb, 0)

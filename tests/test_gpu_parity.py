@@ -297,7 +297,9 @@ def test_l64_multinomial_sampled_step_parity(layout):
 
 
 @pytest.mark.slow
-def test_l128_nearest_sampled_step_parity():
-    """L=128, R=100000, nearest, multispin, beta 0 -> 1.0 in 400 steps: step 180 -> 181."""
-    log("L128 sampled")
-    _sampled_step_parity(128, 100_000, "nearest", "msc64", 400, 1.0, 180, 10, PARITY_SEED, 3)
+@pytest.mark.parametrize("layout", ["msc64", "int8"])
+def test_l128_nearest_sampled_step_parity(layout):
+    """L=128, R=100000, nearest, beta 0 -> 1.0 in 400 steps: step 180 -> 181 (the
+    lattice fills most of a CU's LDS, so the sweep takes two words per thread)."""
+    log("L128 sampled", layout)
+    _sampled_step_parity(128, 100_000, "nearest", layout, 400, 1.0, 180, 10, PARITY_SEED, 3)
