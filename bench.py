@@ -201,6 +201,7 @@ def main():
         n = prof["steps"]
         sweep_ms = prof["ms_sweep"] / n
         res_ms = prof["ms_resample"] / n
+        copy_ms = prof["ms_copy"] / n
         meas_ms = prof["ms_measure"] / n
         words = prof["sweep_words"] / n
         calls = prof["philox_calls"] / n
@@ -219,6 +220,8 @@ def main():
             "philox_calls_per_word": calls / words if words else 0.0,
             "sweep_alu_tops": achieved_tops,
             "resample_copy_bytes": copy_bytes,
+            "copy_us_per_step": copy_ms * 1e3,
+            "copy_hbm_gbs": copy_bytes / (copy_ms * 1e-3) / 1e9,
             "beta_f_error_per_spin": {"at_last_step": err[-1], "max": max(err)},
             "beta_last": recs[-1]["beta"],
             "sweep_geometry": prof["geometry"],
@@ -259,6 +262,10 @@ def main():
     roof = {"bound": "alu", "kernel": "k_sweep<msc64>", "achieved": head["sweep_alu_tops"],
             "peak": VALU_PEAK_TOPS, "unit": "Tops/s (32-bit VALU lane-ops)",
             "frac": head["sweep_alu_tops"] / VALU_PEAK_TOPS, "traffic": traffic}
+    # the HBM-bound kernel of the step: copy / compaction of the population
+    copy_roof = {"bound": "hbm", "kernel": "k_gather<%s>" % head_layout,
+                 "achieved": head["copy_hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": head["copy_hbm_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic("k_gather")}
     out = {
         "metric": "spin-flip attempts/ns + resample/step (L=64,R=1e5); βF error vs exact",
         "value": head["attempts_per_ns"], "unit": "attempts/ns", "n_gpus": 1, "steps": K,
@@ -271,6 +278,7 @@ def main():
                    "steps_timed": "1..%d" % K},
         "resample_us_per_step": head["resample_us_per_step"],
         "roofline": roof,
+        "copy_roofline": copy_roof,
         "layouts": results,
         "workloads": extra,
     }

@@ -186,10 +186,13 @@ pa_status pa_adaptive_dbeta(pa_ctx *ctx, double alpha_target, double dbeta_max, 
 pa_status pa_profile(pa_ctx *ctx, int32_t enable);
 
 /* Totals since profiling was enabled: steps timed, summed milliseconds of the
- * three phases, Philox calls and 64-replica words updated by the sweeps.
+ * three phases (resampling, sweeps, measurement), Philox calls and 64-replica
+ * words updated by the sweeps, and the part of the resampling phase spent in
+ * the copy / compaction kernel (ms_copy).  Any output may be NULL.
  * Synchronises. */
 pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, double *ms_sweep,
-                          double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words);
+                          double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words,
+                          double *ms_copy);
 
 /* Launch geometry of the sweep kernel for the runs of lattice side L: threads
  * per block (a multiple of 64 in [64, 1024]) and 64-replica groups per block

@@ -108,7 +108,8 @@ SIGNATURES = {
     "pa_get_sweep_launch": (_i32, [_vp, _i32, _P(_i32), _P(_i32), _P(_i32)]),
     "pa_batch_set_sweep_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
     "pa_batch_get_sweep_launch": (_i32, [_vp, _i32, _P(_i32), _P(_i32), _P(_i32)]),
-    "pa_profile_read": (_i32, [_vp, _P(_i32), _P(_dbl), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64)]),
+    "pa_profile_read": (_i32, [_vp, _P(_i32), _P(_dbl), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64),
+                               _P(_dbl)]),
 }
 
 
@@ -285,12 +286,13 @@ class Run:
 
     def profile_read(self) -> dict:
         n = ctypes.c_int32()
-        t = [ctypes.c_double() for _ in range(3)]
+        t = [ctypes.c_double() for _ in range(4)]
         calls, words = ctypes.c_uint64(), ctypes.c_uint64()
-        _check(lib().pa_profile_read(self.h, ctypes.byref(n), *[ctypes.byref(x) for x in t],
-                                     ctypes.byref(calls), ctypes.byref(words)), self.h)
+        _check(lib().pa_profile_read(self.h, ctypes.byref(n), *[ctypes.byref(x) for x in t[:3]],
+                                     ctypes.byref(calls), ctypes.byref(words),
+                                     ctypes.byref(t[3])), self.h)
         return {"steps": n.value, "ms_resample": t[0].value, "ms_sweep": t[1].value,
-                "ms_measure": t[2].value, "philox_calls": calls.value,
+                "ms_measure": t[2].value, "ms_copy": t[3].value, "philox_calls": calls.value,
                 "sweep_words": words.value}
 
     def anneal_step_adaptive(self, alpha_target: float, beta_final: float):

@@ -223,6 +223,8 @@ hipError_t g_config_err = hipSuccess;
 }  // namespace
 
 // ----------------------------------------------------------------------------
+constexpr int kProfEvents = 5;  // before counts, copy, sweeps, measurement, and after
+
 struct pa_batch {
     std::vector<pa_config> cfg;
     std::vector<std::vector<double>> betas;
@@ -241,7 +243,7 @@ struct pa_batch {
     std::vector<std::vector<int32_t>> class_maps;  // host copies of uploaded sweep maps
     // phase timing (pa_profile)
     bool profiling = false;
-    std::vector<hipEvent_t> events;  // 4 per profiled step
+    std::vector<hipEvent_t> events;  // kProfEvents per profiled step
     int profiled_steps = 0;
 };
 
@@ -460,19 +462,21 @@ pa_status engine_step(pa_batch *B) {
     if (!B->profiling) {
         PA_HIP(B, launch_step(B->lc));
     } else {
-        const size_t base = (size_t)B->profiled_steps * 4;
-        while (B->events.size() < base + 4) {
+        const size_t base = (size_t)B->profiled_steps * kProfEvents;
+        while (B->events.size() < base + kProfEvents) {
             hipEvent_t ev;
             PA_HIP(B, hipEventCreate(&ev));
             B->events.push_back(ev);
         }
         PA_HIP(B, hipEventRecord(B->events[base], B->stream));
-        PA_HIP(B, launch_resample(B->lc));
+        PA_HIP(B, launch_counts(B->lc));
         PA_HIP(B, hipEventRecord(B->events[base + 1], B->stream));
-        PA_HIP(B, launch_sweeps(B->lc, 0));
+        PA_HIP(B, launch_copy(B->lc));
         PA_HIP(B, hipEventRecord(B->events[base + 2], B->stream));
-        PA_HIP(B, launch_reduce(B->lc));
+        PA_HIP(B, launch_sweeps(B->lc, 0));
         PA_HIP(B, hipEventRecord(B->events[base + 3], B->stream));
+        PA_HIP(B, launch_reduce(B->lc));
+        PA_HIP(B, hipEventRecord(B->events[base + 4], B->stream));
         ++B->profiled_steps;
     }
     for (auto &s : B->host_step) ++s;
@@ -825,24 +829,27 @@ pa_status pa_profile(pa_ctx *ctx, int32_t enable) {
 }
 
 pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, double *ms_sweep,
-                          double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words) {
+                          double *ms_measure, uint64_t *philox_calls, uint64_t *sweep_words,
+                          double *ms_copy) {
     if (!ctx) return fail(nullptr, PA_ERR_ARG, "NULL handle");
     pa_batch *B = &ctx->b;
     RunState s;
     pa_status e = read_state(B, 0, &s);
     if (e) return e;
-    double t[3] = {0, 0, 0};
+    double t[kProfEvents - 1] = {0, 0, 0, 0};  // counts, copy, sweep, measure
     for (int k = 0; k < B->profiled_steps; ++k) {
-        for (int ph = 0; ph < 3; ++ph) {
+        for (int ph = 0; ph < kProfEvents - 1; ++ph) {
             float ms = 0;
-            PA_HIP(B, hipEventElapsedTime(&ms, B->events[4 * k + ph], B->events[4 * k + ph + 1]));
+            PA_HIP(B, hipEventElapsedTime(&ms, B->events[kProfEvents * k + ph],
+                                          B->events[kProfEvents * k + ph + 1]));
             t[ph] += ms;
         }
     }
     if (n_steps) *n_steps = B->profiled_steps;
-    if (ms_resample) *ms_resample = t[0];
-    if (ms_sweep) *ms_sweep = t[1];
-    if (ms_measure) *ms_measure = t[2];
+    if (ms_resample) *ms_resample = t[0] + t[1];
+    if (ms_copy) *ms_copy = t[1];
+    if (ms_sweep) *ms_sweep = t[2];
+    if (ms_measure) *ms_measure = t[3];
     if (philox_calls) *philox_calls = s.philox_calls;
     if (sweep_words) *sweep_words = s.sweep_words;
     return PA_OK;

@@ -40,6 +40,8 @@ hipError_t launch_init(const LaunchCtx &c);
 hipError_t launch_sweeps(const LaunchCtx &c, int init);
 hipError_t launch_reduce(const LaunchCtx &c);
 hipError_t launch_step(const LaunchCtx &c);
+hipError_t launch_counts(const LaunchCtx &c);  // reweighting, copy counts, offsets
+hipError_t launch_copy(const LaunchCtx &c);    // copy / compaction
 hipError_t launch_resample(const LaunchCtx &c);
 hipError_t launch_hist_current(const LaunchCtx &c);
 hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta);

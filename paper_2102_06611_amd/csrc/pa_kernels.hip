@@ -1676,7 +1676,7 @@ hipError_t launch_reduce(const LaunchCtx &c) {
     return hipSuccess;
 }
 
-hipError_t launch_resample(const LaunchCtx &c) {
+hipError_t launch_counts(const LaunchCtx &c) {
     PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
     if (c.any_nearest)
         PA_LAUNCH(k_counts_nearest, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
@@ -1692,8 +1692,18 @@ hipError_t launch_resample(const LaunchCtx &c) {
                   c.slots.map);
     }
     PA_LAUNCH(k_offsets, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+    return hipSuccess;
+}
+
+hipError_t launch_copy(const LaunchCtx &c) {
     PA_LAUNCH(k_gather, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
     return hipSuccess;
+}
+
+hipError_t launch_resample(const LaunchCtx &c) {
+    hipError_t e = launch_counts(c);
+    if (e != hipSuccess) return e;
+    return launch_copy(c);
 }
 
 hipError_t launch_step(const LaunchCtx &c) {
