@@ -263,9 +263,9 @@ def main():
             "peak": VALU_PEAK_TOPS, "unit": "Tops/s (32-bit VALU lane-ops)",
             "frac": head["sweep_alu_tops"] / VALU_PEAK_TOPS, "traffic": traffic}
     # the HBM-bound kernel of the step: copy / compaction of the population
-    copy_roof = {"bound": "hbm", "kernel": "k_gather<%s>" % head_layout,
+    copy_roof = {"bound": "hbm", "kernel": "k_gather_%s" % head_layout,
                  "achieved": head["copy_hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": head["copy_hbm_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic("k_gather")}
+                 "frac": head["copy_hbm_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic("k_gather_%s" % head_layout)}
     out = {
         "metric": "spin-flip attempts/ns + resample/step (L=64,R=1e5); βF error vs exact",
         "value": head["attempts_per_ns"], "unit": "attempts/ns", "n_gpus": 1, "steps": K,

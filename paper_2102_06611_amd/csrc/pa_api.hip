@@ -420,9 +420,12 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         if (e) return e;
     }
     lc.any_nearest = lc.any_multi = false;
+    lc.any_msc = lc.any_int8 = false;
     for (int r = 0; r < n; ++r) {
         if (cfgs[r].resample == PA_RESAMPLE_MULTINOMIAL) lc.any_multi = true;
         else lc.any_nearest = true;
+        if (cfgs[r].layout == PA_LAYOUT_MSC64) lc.any_msc = true;
+        else lc.any_int8 = true;
     }
     PA_HIP(B, launch_init(lc));
     PA_HIP(B, launch_sweeps(lc, 1));

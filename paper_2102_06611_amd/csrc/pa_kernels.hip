@@ -8,7 +8,7 @@
 //                  counts (Eq. taus / resampling-factors)
 //   k_counts_* / k_multi_*   copy counts r_j and per-block partial sums
 //   k_offsets      exclusive prefix sum of r_j (tree order of the children), R_i
-//   k_gather       children <- parents: spins and family labels
+//   k_gather_*     children <- parents: spins and family labels
 //   k_sweep        theta checkerboard Metropolis sweeps in LDS + E, M
 //   k_reduce       population sums, family statistics, next energy histogram
 //   k_record       record i; the new population becomes current
@@ -584,75 +584,111 @@ __device__ __forceinline__ uint64_t net_expand(uint64_t x, const Network &n) {
 constexpr int kGatherPg = 4;      // int8: parent groups staged per pass
 constexpr int kGatherSites = 64;  // int8: site rows per pass
 
-__global__ void __launch_bounds__(256) k_gather(const RunDesc *runs, WorkMap map) {
-    __shared__ u32x4 stage[kGatherPg * kGatherSites * 4];  // int8: groups x rows x 64 bytes
+// Shared start of both gathers: the destination group of the block, the
+// parent of each lane's child and the family labels; false if there is no
+// work (error, or the group lies past the new population).
+struct GatherJob {
+    const RunDesc *rd;
+    int gd, Rn, Rp, cur, nb, N, p, nv, g_first, g_last;
+};
+__device__ __forceinline__ bool gather_start(const RunDesc *runs, const WorkMap &map, int layout,
+                                             GatherJob *j) {
     int gd;
     const RunDesc &rd = runs[map_block(map, xcd_swizzle(blockIdx.x, gridDim.x), &gd)];
     RunState *st = rd.st;
-    if (st->err) return;
+    if (st->err || rd.layout != layout) return false;
     const int Rn = st->R_new, Rp = st->R_cur;
-    if (gd * kLanes >= Rn) return;
-    const int cur = st->cur, nb = cur ^ 1, N = rd.N;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (gd * kLanes >= Rn) return false;
+    const int cur = st->cur, nb = cur ^ 1;
+    const int lane = threadIdx.x & 63;
     const int c = gd * kLanes + lane;
     const int p = c < Rn ? rd.par[c] : -1;  // the last j with off[j] <= c
-    if (wave == 0 && c < rd.C) rd.fam[nb][c] = p >= 0 ? rd.fam[cur][p] : 0;
+    if ((threadIdx.x >> 6) == 0 && c < rd.C) rd.fam[nb][c] = p >= 0 ? rd.fam[cur][p] : 0;
     const int nv = __builtin_amdgcn_readfirstlane(min(kLanes, Rn - gd * kLanes));
-    const int g_first = __builtin_amdgcn_readlane(p, 0) >> 6;
-    const int g_last = __builtin_amdgcn_readlane(p, nv - 1) >> 6;
-    if (rd.layout == PA_LAYOUT_MSC64) {
-        const uint64_t *src = rd.ms[cur];
-        uint64_t *dst = rd.ms[nb] + (size_t)gd * N;
-        const int p_prev = __shfl_up(p, 1, 64);
-        const bool live = lane < nv;
-        const uint64_t D = __ballot(live && (lane == 0 || p != p_prev));  // run heads
-        const uint64_t F = __ballot(live && lane > 0 && p == p_prev);     // copies after a head
-        const Network ND = network_masks(D);
-        const int c_lo = gd * kLanes, c_hi = gd * kLanes + nv;
-        for (int site0 = wave * 256; site0 < N; site0 += nw * 256) {
-            const int sb = site0 + 4 * lane;
-            const bool in = sb < N;  // N = L^2 is a multiple of 4
-            uint64_t S[4] = {0, 0, 0, 0};
-            int shift = 0;
-            for (int pg = g_first; pg <= g_last; ++pg) {
-                // parents j = 64 pg + k of this group that have a copy in [c_lo, c_hi)
-                const int j = pg * kLanes + lane;
-                bool feeds = false;
-                if (j < Rp) {
-                    const int o0 = rd.off[j], o1 = rd.off[j + 1];
-                    feeds = o1 > o0 && o0 < c_hi && o1 > c_lo;
-                }
-                const uint64_t P = __ballot(feeds);
-                if (!P) continue;
-                const Network NP = network_masks(P);
-                if (in) {
-                    const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(src + (size_t)pg * N + sb);
-                    const ulonglong2 v0 = q[0], v1 = q[1];
-                    S[0] |= net_compress(v0.x, NP) << shift;
-                    S[1] |= net_compress(v0.y, NP) << shift;
-                    S[2] |= net_compress(v1.x, NP) << shift;
-                    S[3] |= net_compress(v1.y, NP) << shift;
-                }
-                shift += __popcll(P);
-            }
-            if (in) {
-                uint64_t o[4];
+    *j = GatherJob{&rd, gd, Rn, Rp, cur, nb, rd.N, p, nv,
+                   __builtin_amdgcn_readlane(p, 0) >> 6, __builtin_amdgcn_readlane(p, nv - 1) >> 6};
+    return true;
+}
+
+// Child word of four sites from the concatenated surviving-parent bits S.
+__device__ __forceinline__ void gather_emit(const uint64_t *S, const Network &ND, uint64_t F,
+                                            uint64_t *o) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    uint64_t x = net_expand(S[k], ND);
-                    uint64_t Fk = F;
-                    for (int sh = 1; Fk; sh <<= 1) {  // OR-fill runs of copies (uniform)
-                        x |= (x << sh) & Fk;
-                        Fk &= Fk << sh;
-                    }
-                    o[k] = x;
-                }
-                ulonglong2 *q = reinterpret_cast<ulonglong2 *>(dst + sb);
-                q[0] = ulonglong2{o[0], o[1]};
-                q[1] = ulonglong2{o[2], o[3]};
-            }
+    for (int k = 0; k < 4; ++k) {
+        uint64_t x = net_expand(S[k], ND);
+        uint64_t Fk = F;
+        for (int sh = 1; Fk; sh <<= 1) {  // OR-fill runs of copies (uniform)
+            x |= (x << sh) & Fk;
+            Fk &= Fk << sh;
         }
-    } else {
+        o[k] = x;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gather_msc64(const RunDesc *runs, WorkMap map) {
+    GatherJob jb;
+    if (!gather_start(runs, map, PA_LAYOUT_MSC64, &jb)) return;
+    const RunDesc &rd = *jb.rd;
+    const int N = jb.N, p = jb.p, nv = jb.nv, g_first = jb.g_first, g_last = jb.g_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.ms[jb.cur]));
+    const gptr<u32x4> dst = global(reinterpret_cast<u32x4 *>(rd.ms[jb.nb] + (size_t)jb.gd * N));
+    const int p_prev = __shfl_up(p, 1, 64);
+    const bool live = lane < nv;
+    const uint64_t D = __ballot(live && (lane == 0 || p != p_prev));  // run heads
+    const uint64_t F = __ballot(live && lane > 0 && p == p_prev);     // copies after a head
+    const Network ND = network_masks(D);
+    const int c_lo = jb.gd * kLanes, c_hi = jb.gd * kLanes + nv;
+    // parents j = 64 pg + k that have a copy in [c_lo, c_hi): the selector P of pg
+    auto selector = [&](int pg) -> uint64_t {
+        const int j = pg * kLanes + lane;
+        bool feeds = false;
+        if (j < jb.Rp) {
+            const int o0 = rd.off[j], o1 = rd.off[j + 1];
+            feeds = o1 > o0 && o0 < c_hi && o1 > c_lo;
+        }
+        return __ballot(feeds);
+    };
+    // each 256-site stretch of a wavefront: per feeding parent group, its selector
+    // (a ballot over the parents' offsets) and the compressed parent words
+    for (int site0 = wave * 256; site0 < N; site0 += nw * 256) {
+        const int sb = site0 + 4 * lane;
+        const bool in = sb < N;
+        uint64_t S[4] = {0, 0, 0, 0};
+        int shift = 0;
+        for (int pg = g_first; pg <= g_last; ++pg) {
+            const uint64_t P = selector(pg);
+            if (!P) continue;
+            const Network NP = network_masks(P);
+            if (in) {
+                const size_t q = ((size_t)pg * N + sb) / 2;
+                const u32x4 v0 = src[q], v1 = src[q + 1];
+                S[0] |= net_compress(((uint64_t)v0.y << 32) | v0.x, NP) << shift;
+                S[1] |= net_compress(((uint64_t)v0.w << 32) | v0.z, NP) << shift;
+                S[2] |= net_compress(((uint64_t)v1.y << 32) | v1.x, NP) << shift;
+                S[3] |= net_compress(((uint64_t)v1.w << 32) | v1.z, NP) << shift;
+            }
+            shift += __popcll(P);
+        }
+        if (in) {
+            uint64_t o[4];
+            gather_emit(S, ND, F, o);
+            dst[sb / 2] = u32x4{(uint32_t)o[0], (uint32_t)(o[0] >> 32), (uint32_t)o[1],
+                                (uint32_t)(o[1] >> 32)};
+            dst[sb / 2 + 1] = u32x4{(uint32_t)o[2], (uint32_t)(o[2] >> 32), (uint32_t)o[3],
+                                    (uint32_t)(o[3] >> 32)};
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gather_int8(const RunDesc *runs, WorkMap map) {
+    __shared__ u32x4 stage[kGatherPg * kGatherSites * 4];  // groups x rows x 64 bytes
+    GatherJob jb;
+    if (!gather_start(runs, map, PA_LAYOUT_INT8, &jb)) return;
+    const RunDesc &rd = *jb.rd;
+    const int N = jb.N, p = jb.p, g_first = jb.g_first, g_last = jb.g_last;
+    const int cur = jb.cur, nb = jb.nb, gd = jb.gd;
+    {
         // thread -> dword k (children 4k .. 4k + 3) of site rows sl, sl + 16, ...
         // of a chunk of kGatherSites rows
         const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.s8[cur]));
@@ -1696,7 +1732,10 @@ hipError_t launch_counts(const LaunchCtx &c) {
 }
 
 hipError_t launch_copy(const LaunchCtx &c) {
-    PA_LAUNCH(k_gather, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
+    if (c.any_msc)
+        PA_LAUNCH(k_gather_msc64, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
+    if (c.any_int8)
+        PA_LAUNCH(k_gather_int8, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
     return hipSuccess;
 }
 
