@@ -66,7 +66,6 @@ def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial"
     run = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream)
     geometry = autotune.apply(run, L, R, layout) or run.sweep_launch(L)
     run.sync()
-    run.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(K):
@@ -74,9 +73,21 @@ def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial"
     run.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = run.profile_read()
     recs = [run.observables(i) for i in range(K + 1)]
     attempts = sum(r["R_i"] for r in recs[1:]) * L * L * THETA
+    # the same K steps again with phase timing and Philox-call counting (the
+    # run is deterministic: same populations, same calls)
+    prun = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream)
+    autotune.apply(prun, L, R, layout)
+    prun.profile(True)
+    for _ in range(K):
+        prun.anneal_step()
+    prun.sync()
+    prof = prun.profile_read()
+    last = prun.observables(K)
+    if (last["R_i"], last["minus_beta_F"]) != (recs[K]["R_i"], recs[K]["minus_beta_F"]):
+        raise RuntimeError("the profiled run differs from the timed run")
+    prun.close()
     prof["geometry"] = list(geometry)
     return run, wall, prof, recs, attempts
 

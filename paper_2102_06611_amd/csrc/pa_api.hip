@@ -821,12 +821,13 @@ pa_status pa_profile(pa_ctx *ctx, int32_t enable) {
     if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
     PA_HIP(B, hipStreamSynchronize(B->stream));
     B->profiling = enable != 0;
-    if (B->profiling) {
-        B->profiled_steps = 0;
-        for (int r = 0; r < B->n; ++r) {
-            unsigned long long zero[2] = {0, 0};
-            PA_HIP(B, hipMemcpy(&B->desc[r].st->philox_calls, zero, sizeof zero, hipMemcpyHostToDevice));
-        }
+    if (B->profiling) B->profiled_steps = 0;
+    for (int r = 0; r < B->n; ++r) {
+        const int32_t on = B->profiling ? 1 : 0;
+        PA_HIP(B, hipMemcpy(&B->desc[r].st->count_calls, &on, sizeof on, hipMemcpyHostToDevice));
+        if (!B->profiling) continue;
+        unsigned long long zero[2] = {0, 0};
+        PA_HIP(B, hipMemcpy(&B->desc[r].st->philox_calls, zero, sizeof zero, hipMemcpyHostToDevice));
     }
     return PA_OK;
 }

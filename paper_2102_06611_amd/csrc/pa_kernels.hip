@@ -897,10 +897,13 @@ __device__ __forceinline__ void tie_one(uint64_t &und, uint64_t eq1, uint32_t L4
     flip |= ((v >> 6) < t) ? bit : 0ull;
 }
 
+// most tied words have one tie: the later slots are skipped once none is left
 __device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t L4, uint32_t L8,
                                          const U4 &x, uint64_t &flip) {
     tie_one(und, eq1, L4, L8, x.x, flip);
+    if (und == 0) return;
     tie_one(und, eq1, L4, L8, x.y, flip);
+    if (und == 0) return;
     tie_one(und, eq1, L4, L8, x.z, flip);
     tie_one(und, eq1, L4, L8, x.w, flip);
 }
@@ -909,15 +912,20 @@ __device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t L
 // a_k = s XOR n_k (antiparallel neighbours), A = sum a_k and dE = 8 - 4A:
 // A >= 2 (dE <= 0) always flips; A = 1 (dE = 4) and A = 0 (dE = 8) flip iff
 // u32 < t4 / t8.  The top six bits of u32 are compared bit plane by bit plane
-// from the most significant one, generating planes only while some lane is
-// still tied with its threshold; the lanes tied after six planes are decided
-// by one comparison of fresh low bits each.  This equals the full 32-bit
-// comparison.
+// from the most significant one; the lanes still tied with their threshold
+// after six planes are decided by one comparison of fresh low bits each.
+// This equals the full 32-bit comparison.  All three plane calls are made:
+// a word has some twenty lanes with dE > 0, so a wavefront nearly always has
+// a word that needs the third, and a loop that stops early costs more than it
+// saves.  With count, the calls the word needs (plane pairs while a lane is
+// still tied, and tie calls) are added: plane calls to *wcalls (the same in
+// every lane: the wavefront's total), tie calls to *calls.
 __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, uint64_t a3,
                                                     uint64_t a4, uint64_t valid, uint64_t t4,
                                                     uint64_t t8, bool all4, bool all8,
                                                     uint32_t k0, uint32_t k1, uint32_t w,
-                                                    uint32_t g, uint32_t h, uint32_t *calls) {
+                                                    uint32_t g, uint32_t h, bool count,
+                                                    uint32_t *calls, uint32_t *wcalls) {
     const WordClass2 c = classes(a1, a2, a3, a4);
     const uint64_t eq1 = c.eq1;
     uint64_t flip = c.ge2 & valid;
@@ -932,8 +940,9 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
     Lanes s{(uint32_t)und, (uint32_t)(und >> 32), (uint32_t)flip, (uint32_t)(flip >> 32)};
     const uint32_t el = (uint32_t)eq1, eh = (uint32_t)(eq1 >> 32);
-    uint32_t p = 0;
-    for (; (s.ul | s.uh) != 0 && p < kPlanePairs; ++p) {
+#pragma unroll
+    for (uint32_t p = 0; p < kPlanePairs; ++p) {
+        if (count) *wcalls += (uint32_t)__popcll(__ballot((s.ul | s.uh) != 0));
         const U4 x = philox(k0, k1, w, g, h, kTagSweep | p);
         plane_pair<1>(&s, &el, &eh, T4, T8, p, &x);
     }
@@ -944,20 +953,22 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
         const U4 x = philox(k0, k1, w, g, h, kTagTie | q);
         tie_call(und, eq1, T4 & kLow26, T8 & kLow26, x, flip);
     }
-    *calls += p + q;
+    if (count) *calls += q;
     return flip;
 }
 
 // The same comparison for K words in one lane at once: their Philox chains
 // are independent instruction streams (for launches too large for more than
-// one block per CU, where few wavefronts share a SIMD).
+// one block per CU, where few wavefronts share a SIMD).  Calls are counted as
+// in metropolis_word.
 // In: nb[k][0..3] the neighbour words and s0[k] the site word; out: flip[k].
 template <int K>
 __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const uint64_t *s0,
                                                  const uint64_t *valid, uint64_t t4, uint64_t t8,
                                                  bool all4, bool all8, uint32_t k0, uint32_t k1,
                                                  const uint32_t *w, const uint32_t *g, uint32_t h,
-                                                 uint64_t *flip, uint32_t *calls) {
+                                                 uint64_t *flip, bool count, uint32_t *calls,
+                                                 uint32_t *wcalls) {
     Lanes s[K];
     uint32_t el[K], eh[K];
     uint64_t eq1[K];
@@ -980,18 +991,14 @@ __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const
     // the thresholds are the same for every lane: keep their bits in scalar registers
     const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
-    for (uint32_t p = 0; p < kPlanePairs; ++p) {
-        bool any = false;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bool open = (s[k].ul | s[k].uh) != 0;
-            any |= open;
-            *calls += open ? 1u : 0u;
-        }
-        if (!any) break;
+    for (uint32_t p = 0; p < kPlanePairs; ++p) {
         U4 x[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) x[k] = philox(k0, k1, w[k], g[k], h, kTagSweep | p);
+        for (int k = 0; k < K; ++k) {
+            if (count) *wcalls += (uint32_t)__popcll(__ballot((s[k].ul | s[k].uh) != 0));
+            x[k] = philox(k0, k1, w[k], g[k], h, kTagSweep | p);
+        }
         plane_pair<K>(s, el, eh, T4, T8, p, x);
     }
     uint64_t und[K];
@@ -1005,7 +1012,7 @@ __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             any |= und[k] != 0;
-            *calls += und[k] != 0 ? 1u : 0u;
+            if (count) *calls += und[k] != 0 ? 1u : 0u;
         }
         if (!any) break;
         U4 x[K];
@@ -1249,7 +1256,8 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     const uint64_t last_valid = lane_mask(Rn - (g0 + ng - 1) * kLanes);
     const int P = hl.P;
     const uint32_t k0 = rd.key0, k1 = rd.key1;
-    uint32_t calls = 0;
+    const bool count = __builtin_amdgcn_readfirstlane(st->count_calls) != 0;  // uniform
+    uint32_t calls = 0, wcalls = 0;
     for (int s = 0; s < theta; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
@@ -1264,7 +1272,8 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
                                                        s0 ^ lat[site - P], s0 ^ lat[site + P], valid,
                                                        t4, t8, all4, all8, k0, k1,
                                                        (uint32_t)(wk.y * half + wk.xh),
-                                                       (uint32_t)(g0 + wk.gl), h, &calls);
+                                                       (uint32_t)(g0 + wk.gl), h, count, &calls,
+                                                       &wcalls);
                     lat[site] = s0 ^ f;
                     if (ROWS)
                         walk_advance_rows(wk, step);
@@ -1297,7 +1306,7 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
                             walk_advance(wk, step);
                     }
                     metropolis_words<ILP>(nbr, s0, valid, t4, t8, all4, all8, k0, k1, wi, gi, h, f,
-                                          &calls);
+                                          count, &calls, &wcalls);
 #pragma unroll
                     for (int k = 0; k < ILP; ++k)
                         if (f[k]) lat[site[k]] = s0[k] ^ f[k];
@@ -1341,11 +1350,10 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
             }
         }
     }
-    {  // Philox calls of this block (one atomic per wave)
-        const uint64_t c64 = wave_sum_i64((int64_t)calls);
-        if ((tid & 63) == 0 && theta > 0) atomicAdd(&st->philox_calls, (unsigned long long)c64);
-        if (tid == 0 && theta > 0)
-            atomicAdd(&st->sweep_words, (unsigned long long)theta * (unsigned long long)N * ng);
+    if (count && theta > 0) {  // Philox calls of this block (one atomic per wave)
+        const uint64_t c64 = (uint64_t)wave_sum_i64((int64_t)calls) + wcalls;
+        if ((tid & 63) == 0) atomicAdd(&st->philox_calls, (unsigned long long)c64);
+        if (tid == 0) atomicAdd(&st->sweep_words, (unsigned long long)theta * (unsigned long long)N * ng);
     }
     __syncthreads();
     for (int k = tid; k < ng * kLanes; k += nt) {
