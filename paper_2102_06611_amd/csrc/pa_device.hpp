@@ -125,10 +125,25 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // 0xF0 ^ 0xCC ^ 0xAA
 }
 
+// In every use the counter word c3 (the stream tag) is the same across a
+// wavefront: the first round XORs it with the key first (no three-input XOR
+// with two scalar operands, one of which would need a move).
 __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
                                      uint32_t c2, uint32_t c3) {
+    {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 1; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);

@@ -921,8 +921,8 @@ __device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t L
 // still tied, and tie calls) are added: plane calls to *wcalls (the same in
 // every lane: the wavefront's total), tie calls to *calls.
 __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, uint64_t a3,
-                                                    uint64_t a4, uint64_t valid, uint64_t t4,
-                                                    uint64_t t8, bool all4, bool all8,
+                                                    uint64_t a4, uint64_t valid, uint32_t T4,
+                                                    uint32_t T8, bool all4, bool all8,
                                                     uint32_t k0, uint32_t k1, uint32_t w,
                                                     uint32_t g, uint32_t h, bool count,
                                                     uint32_t *calls, uint32_t *wcalls) {
@@ -935,9 +935,6 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
         if (all4) { flip |= e1; und &= ~e1; }
         if (all8) { flip |= e0; und &= ~e0; }
     }
-    // the thresholds are the same for every lane: keep their bits in scalar registers
-    const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
-    const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
     Lanes s{(uint32_t)und, (uint32_t)(und >> 32), (uint32_t)flip, (uint32_t)(flip >> 32)};
     const uint32_t el = (uint32_t)eq1, eh = (uint32_t)(eq1 >> 32);
 #pragma unroll
@@ -953,7 +950,7 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
         const U4 x = philox(k0, k1, w, g, h, kTagTie | q);
         tie_call(und, eq1, T4 & kLow26, T8 & kLow26, x, flip);
     }
-    if (count) *calls += q;
+    *calls += q;  // read only when counting
     return flip;
 }
 
@@ -964,7 +961,7 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
 // In: nb[k][0..3] the neighbour words and s0[k] the site word; out: flip[k].
 template <int K>
 __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const uint64_t *s0,
-                                                 const uint64_t *valid, uint64_t t4, uint64_t t8,
+                                                 const uint64_t *valid, uint32_t T4, uint32_t T8,
                                                  bool all4, bool all8, uint32_t k0, uint32_t k1,
                                                  const uint32_t *w, const uint32_t *g, uint32_t h,
                                                  uint64_t *flip, bool count, uint32_t *calls,
@@ -988,9 +985,6 @@ __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const
         el[k] = (uint32_t)c.eq1;
         eh[k] = (uint32_t)(c.eq1 >> 32);
     }
-    // the thresholds are the same for every lane: keep their bits in scalar registers
-    const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
-    const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
 #pragma unroll
     for (uint32_t p = 0; p < kPlanePairs; ++p) {
         U4 x[K];
@@ -1012,7 +1006,7 @@ __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             any |= und[k] != 0;
-            if (count) *calls += und[k] != 0 ? 1u : 0u;
+            *calls += und[k] != 0 ? 1u : 0u;  // read only when counting
         }
         if (!any) break;
         U4 x[K];
@@ -1187,9 +1181,14 @@ struct MeasCounters {
 // the words tid, tid + nt, ... of a colour.  After each half-sweep the ghost
 // cells are refreshed.  Afterwards each replica's E = 2U - 2N (U antiparallel
 // bonds) and M are measured.  With init != 0 no sweep is done.
+// WALK: kWalkAny (general incremental walk), kWalkRows (the stride nt is a
+// whole number of rows), kWalkOneGroup (also one group per block: a thread's
+// column is fixed, its LDS index advances by a constant and its word index in
+// the colour is the loop index).
 constexpr int kMaxGroupsPerBlock = 8;
+constexpr int kWalkAny = 0, kWalkRows = 1, kWalkOneGroup = 2;
 
-template <int LAYOUT, bool ROWS, int ILP>
+template <int LAYOUT, int WALK, int ILP>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ILP == 1 ? 8 : 4)))
 k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     extern __shared__ uint64_t lat[];
@@ -1252,17 +1251,42 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     const int i = st->step + 1;
     const uint64_t t4 = st->t4, t8 = st->t8;
     const bool all4 = t4 >= (1ull << 32), all8 = t8 >= (1ull << 32);
+    // the thresholds are the same for every lane: keep their bits in scalar registers
+    const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
+    const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
     const int words = ng * (N >> 1);  // sites of one colour, all groups of the block
     const uint64_t last_valid = lane_mask(Rn - (g0 + ng - 1) * kLanes);
     const int P = hl.P;
     const uint32_t k0 = rd.key0, k1 = rd.key1;
     const bool count = __builtin_amdgcn_readfirstlane(st->count_calls) != 0;  // uniform
+    // kWalkOneGroup: the thread's column xh1, first row y1 and row stride dy1
+    const int y1 = tid / half, xh1 = tid - y1 * half, dy1 = nt / half, dsite1 = dy1 * P;
     uint32_t calls = 0, wcalls = 0;
     for (int s = 0; s < theta; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
             WordWalk wk = walk_start(tid, hl);
-            if (ILP == 1) {
+            // next row of this thread's column (kWalkOneGroup): with dy1 odd the
+            // site alternates between the two columns 2 xh1 and 2 xh1 + 1
+            const int par1 = (colour + y1) & 1;
+            int site1 = hl.at(0, 2 * xh1 + par1, y1), dlt1 = dsite1 + ((dy1 & 1) ? 1 - 2 * par1 : 0);
+            auto advance1 = [&]() {
+                site1 += dlt1;
+                dlt1 = 2 * dsite1 - dlt1;
+            };
+            if (ILP == 1 && WALK == kWalkOneGroup) {
+                for (int w = tid; w < words; w += nt) {
+                    const int site = site1;
+                    const uint64_t s0 = lat[site];
+                    const uint64_t f = metropolis_word(s0 ^ lat[site + 1], s0 ^ lat[site - 1],
+                                                       s0 ^ lat[site - P], s0 ^ lat[site + P],
+                                                       last_valid, T4, T8, all4, all8, k0, k1,
+                                                       (uint32_t)w, (uint32_t)g0, h, count, &calls,
+                                                       &wcalls);
+                    lat[site] = s0 ^ f;
+                    advance1();
+                }
+            } else if (ILP == 1) {
                 for (int idx = tid; idx < words; idx += nt) {
                     const int x = 2 * wk.xh + ((colour + wk.y) & 1);
                     const int site = wk.row + x;
@@ -1270,12 +1294,12 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
                     const uint64_t valid = wk.gl == ng - 1 ? last_valid : ~0ull;
                     const uint64_t f = metropolis_word(s0 ^ lat[site + 1], s0 ^ lat[site - 1],
                                                        s0 ^ lat[site - P], s0 ^ lat[site + P], valid,
-                                                       t4, t8, all4, all8, k0, k1,
+                                                       T4, T8, all4, all8, k0, k1,
                                                        (uint32_t)(wk.y * half + wk.xh),
                                                        (uint32_t)(g0 + wk.gl), h, count, &calls,
                                                        &wcalls);
                     lat[site] = s0 ^ f;
-                    if (ROWS)
+                    if (WALK == kWalkRows)
                         walk_advance_rows(wk, step);
                     else
                         walk_advance(wk, step);
@@ -1289,23 +1313,30 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
 #pragma unroll
                     for (int k = 0; k < ILP; ++k) {
                         const bool live = k == 0 || idx + k * nt < words;
-                        const int x = 2 * wk.xh + ((colour + wk.y) & 1);
-                        site[k] = wk.row + x;
+                        if (WALK == kWalkOneGroup) {
+                            site[k] = site1;
+                            valid[k] = live ? last_valid : 0ull;
+                            wi[k] = (uint32_t)(idx + k * nt);
+                            gi[k] = (uint32_t)g0;
+                            advance1();
+                        } else {
+                            site[k] = wk.row + 2 * wk.xh + ((colour + wk.y) & 1);
+                            valid[k] = !live ? 0ull : (wk.gl == ng - 1 ? last_valid : ~0ull);
+                            wi[k] = (uint32_t)(wk.y * half + wk.xh);
+                            gi[k] = (uint32_t)(g0 + wk.gl);
+                            if (WALK == kWalkRows)
+                                walk_advance_rows(wk, step);
+                            else
+                                walk_advance(wk, step);
+                        }
                         if (!live) site[k] = site[0];  // past the last word: a dummy with no lanes
                         s0[k] = lat[site[k]];
                         nbr[k][0] = lat[site[k] + 1];
                         nbr[k][1] = lat[site[k] - 1];
                         nbr[k][2] = lat[site[k] - P];
                         nbr[k][3] = lat[site[k] + P];
-                        valid[k] = !live ? 0ull : (wk.gl == ng - 1 ? last_valid : ~0ull);
-                        wi[k] = (uint32_t)(wk.y * half + wk.xh);
-                        gi[k] = (uint32_t)(g0 + wk.gl);
-                        if (ROWS)
-                            walk_advance_rows(wk, step);
-                        else
-                            walk_advance(wk, step);
                     }
-                    metropolis_words<ILP>(nbr, s0, valid, t4, t8, all4, all8, k0, k1, wi, gi, h, f,
+                    metropolis_words<ILP>(nbr, s0, valid, T4, T8, all4, all8, k0, k1, wi, gi, h, f,
                                           count, &calls, &wcalls);
 #pragma unroll
                     for (int k = 0; k < ILP; ++k)
@@ -1686,26 +1717,28 @@ hipError_t launch_init(const LaunchCtx &c) {
 // LDS of one sweep block: gpb lattices with their halo
 size_t sweep_lds_bytes(int L, int gpb) { return (size_t)gpb * (L + 2) * (L + 2) * 8; }
 
-// k_sweep instantiation for a layout and sel = rows (bit 0) | two words per thread (bit 1)
-static const void *sweep_kernel(int layout, int sel) {
-    static const void *const fns[2][4] = {
-        {(const void *)k_sweep<0, false, 1>, (const void *)k_sweep<0, true, 1>,
-         (const void *)k_sweep<0, false, 2>, (const void *)k_sweep<0, true, 2>},
-        {(const void *)k_sweep<1, false, 1>, (const void *)k_sweep<1, true, 1>,
-         (const void *)k_sweep<1, false, 2>, (const void *)k_sweep<1, true, 2>}};
-    return fns[layout][sel];
+// k_sweep instantiation for a layout, a word walk and words per thread at once
+static const void *sweep_kernel(int layout, int walk, int ilp) {
+    static const void *const fns[2][3][2] = {
+        {{(const void *)k_sweep<0, kWalkAny, 1>, (const void *)k_sweep<0, kWalkAny, 2>},
+         {(const void *)k_sweep<0, kWalkRows, 1>, (const void *)k_sweep<0, kWalkRows, 2>},
+         {(const void *)k_sweep<0, kWalkOneGroup, 1>, (const void *)k_sweep<0, kWalkOneGroup, 2>}},
+        {{(const void *)k_sweep<1, kWalkAny, 1>, (const void *)k_sweep<1, kWalkAny, 2>},
+         {(const void *)k_sweep<1, kWalkRows, 1>, (const void *)k_sweep<1, kWalkRows, 2>},
+         {(const void *)k_sweep<1, kWalkOneGroup, 1>, (const void *)k_sweep<1, kWalkOneGroup, 2>}}};
+    return fns[layout][walk][ilp - 1];
 }
 
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
     for (const auto &cls : c.sweep_classes) {
         const size_t lds = sweep_lds_bytes(cls.L, cls.gpb);
         const bool rows = cls.threads % (cls.L / 2) == 0;  // the word walk moves whole rows
+        const int walk = !rows ? kWalkAny : cls.gpb == 1 ? kWalkOneGroup : kWalkRows;
         // a block that fills a CU's LDS runs alone: two words per thread at once
-        const bool ilp = lds > kMaxSweepLds / 2;
-        const int sel = (rows ? 1 : 0) | (ilp ? 2 : 0);
+        const int ilp = lds > kMaxSweepLds / 2 ? 2 : 1;
         for (int layout = 0; layout < 2; ++layout) {
             if (!(layout == PA_LAYOUT_MSC64 ? cls.has_msc : cls.has_int8)) continue;
-            const void *fn = sweep_kernel(layout, sel);
+            const void *fn = sweep_kernel(layout, walk, ilp);
             void *args[] = {(void *)&c.runs, (void *)&cls.map, (void *)&init, (void *)&cls.gpb};
             hipError_t e = hipLaunchKernel(fn, dim3(cls.total), dim3(cls.threads), args, lds, c.stream);
             if (e != hipSuccess) return e;
@@ -1819,8 +1852,8 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 
 hipError_t configure_kernels() {
     // up to kMaxSweepLds bytes of lattices (with their halo) per sweep block
-    for (int k = 0; k < 8; ++k) {
-        const void *f = sweep_kernel(k >> 2, k & 3);
+    for (int k = 0; k < 12; ++k) {
+        const void *f = sweep_kernel(k / 6, (k / 2) % 3, k % 2 + 1);
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
         if (e != hipSuccess) return e;
     }

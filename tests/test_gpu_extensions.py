@@ -227,8 +227,13 @@ GEOMETRIES = {
     # the thread stride is not a multiple of a row: the word walk carries
     # across rows and groups
     6: ((256, 4), (64, 1), (1024, 2), (128, 8), (512, 1), (192, 3)),
-    # three or four groups fill more than half the LDS: two words per thread
-    64: ((512, 1), (256, 3), (1024, 4), (320, 3)),
+    # three or four groups fill more than half the LDS: two words per thread;
+    # one group per block: a thread keeps its column
+    64: ((512, 1), (256, 3), (1024, 4), (320, 3), (192, 1)),
+    # one group fills more than half the LDS; with 64, 192 or 320 threads a
+    # thread's rows are 1, 3 or 5 apart, so its word alternates between the
+    # two columns of its pair
+    128: ((1024, 1), (192, 1), (64, 1), (320, 1)),
 }
 
 
