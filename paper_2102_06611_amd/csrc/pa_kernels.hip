@@ -545,13 +545,26 @@ __device__ __forceinline__ Network network_masks(uint64_t m) {
 }
 // Selected bits of x, moved to the low end in order (bits of x outside the
 // selector are dropped).
+// A three-input bitwise function (table as for xor3) on the halves of 64-bit
+// words; the builtin returns a signed int, so each half is taken as unsigned
+// before it is widened
+template <int TABLE>
+__device__ __forceinline__ uint64_t bitop3_64(uint64_t a, uint64_t b, uint64_t c) {
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32),
+                                                              (uint32_t)(c >> 32), TABLE);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, TABLE);
+    return ((uint64_t)hi << 32) | lo;
+}
+// (a & ~b) | c and (a & ~b) | (c & b)
+__device__ __forceinline__ uint64_t andn_or(uint64_t a, uint64_t b, uint64_t c) { return bitop3_64<0xBA>(a, b, c); }
+__device__ __forceinline__ uint64_t select_bits(uint64_t a, uint64_t b, uint64_t c) { return bitop3_64<0xB8>(a, b, c); }
 __device__ __forceinline__ uint64_t net_compress(uint64_t x, const Network &n) {
     x &= n.m;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         if (n.mv[i]) {  // uniform
             const uint64_t t = x & n.mv[i];
-            x = (x ^ t) | (t >> (1 << i));
+            x = andn_or(x, n.mv[i], t >> (1 << i));  // (x ^ t) | (t >> 2^i)
         }
     }
     return x;
@@ -560,10 +573,7 @@ __device__ __forceinline__ uint64_t net_compress(uint64_t x, const Network &n) {
 __device__ __forceinline__ uint64_t net_expand(uint64_t x, const Network &n) {
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
-        if (n.mv[i]) {  // uniform
-            const uint64_t t = x << (1 << i);
-            x = (x & ~n.mv[i]) | (t & n.mv[i]);
-        }
+        if (n.mv[i]) x = select_bits(x, n.mv[i], x << (1 << i));  // uniform test
     }
     return x & n.m;
 }
@@ -618,18 +628,26 @@ __device__ __forceinline__ void gather_emit(const uint64_t *S, const Network &ND
         uint64_t x = net_expand(S[k], ND);
         uint64_t Fk = F;
         for (int sh = 1; Fk; sh <<= 1) {  // OR-fill runs of copies (uniform)
-            x |= (x << sh) & Fk;
+            x = bitop3_64<0xF8>(x, x << sh, Fk);  // x | ((x << sh) & Fk)
             Fk &= Fk << sh;
         }
         o[k] = x;
     }
 }
 
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+
+constexpr int kGatherPass = 256;  // multispin: sites of one wavefront pass (four per lane)
+constexpr int kGatherPasses = 4;  // multispin: passes whose loads are in flight together
+
 __global__ void __launch_bounds__(256) k_gather_msc64(const RunDesc *runs, WorkMap map) {
     GatherJob jb;
     if (!gather_start(runs, map, PA_LAYOUT_MSC64, &jb)) return;
     const RunDesc &rd = *jb.rd;
-    const int N = jb.N, p = jb.p, nv = jb.nv, g_first = jb.g_first, g_last = jb.g_last;
+    const int N = jb.N, p = jb.p, nv = jb.nv;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.ms[jb.cur]));
     const gptr<u32x4> dst = global(reinterpret_cast<u32x4 *>(rd.ms[jb.nb] + (size_t)jb.gd * N));
@@ -638,45 +656,56 @@ __global__ void __launch_bounds__(256) k_gather_msc64(const RunDesc *runs, WorkM
     const uint64_t D = __ballot(live && (lane == 0 || p != p_prev));  // run heads
     const uint64_t F = __ballot(live && lane > 0 && p == p_prev);     // copies after a head
     const Network ND = network_masks(D);
-    const int c_lo = jb.gd * kLanes, c_hi = jb.gd * kLanes + nv;
-    // parents j = 64 pg + k that have a copy in [c_lo, c_hi): the selector P of pg
-    auto selector = [&](int pg) -> uint64_t {
-        const int j = pg * kLanes + lane;
-        bool feeds = false;
-        if (j < jb.Rp) {
-            const int o0 = rd.off[j], o1 = rd.off[j + 1];
-            feeds = o1 > o0 && o0 < c_hi && o1 > c_lo;
-        }
-        return __ballot(feeds);
-    };
-    // each 256-site stretch of a wavefront: per feeding parent group, its selector
-    // (a ballot over the parents' offsets) and the compressed parent words
-    for (int site0 = wave * 256; site0 < N; site0 += nw * 256) {
-        const int sb = site0 + 4 * lane;
-        const bool in = sb < N;
-        uint64_t S[4] = {0, 0, 0, 0};
+    // the selector of parent group pg (its parents with a child in this group)
+    // from the children's parents: an OR-scan of the bits 1 << (p mod 64) over
+    // the lanes whose parent lies in the same group leaves it in the last such
+    // lane (the parents ascend with the lane)
+    const int pgl = live ? p >> 6 : INT_MAX;
+    uint64_t sel = live ? 1ull << (p & 63) : 0ull;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(sel, d, 64);
+        const int og = __shfl_up(pgl, d, 64);
+        if (lane >= d && og == pgl) sel |= o;
+    }
+    const int pg_next = __shfl_down(pgl, 1, 64);
+    const uint64_t ends = __ballot(live && (lane == nv - 1 || pg_next != pgl));
+    // chunks of kGatherPasses passes of a wavefront: per feeding parent group
+    // (ascending), its network once and the compressed parent words of every
+    // pass, concatenated in S
+    for (int c0 = wave * kGatherPass * kGatherPasses; c0 < N; c0 += nw * kGatherPass * kGatherPasses) {
+        uint64_t S[kGatherPasses][4] = {};
         int shift = 0;
-        for (int pg = g_first; pg <= g_last; ++pg) {
-            const uint64_t P = selector(pg);
-            if (!P) continue;
+        for (uint64_t m = ends; m; m &= m - 1) {  // uniform
+            const int l = __builtin_ctzll(m);
+            const uint64_t P = readlane64(sel, l);
+            const int pg = __builtin_amdgcn_readlane(pgl, l);
             const Network NP = network_masks(P);
-            if (in) {
-                const size_t q = ((size_t)pg * N + sb) / 2;
-                const u32x4 v0 = src[q], v1 = src[q + 1];
-                S[0] |= net_compress(((uint64_t)v0.y << 32) | v0.x, NP) << shift;
-                S[1] |= net_compress(((uint64_t)v0.w << 32) | v0.z, NP) << shift;
-                S[2] |= net_compress(((uint64_t)v1.y << 32) | v1.x, NP) << shift;
-                S[3] |= net_compress(((uint64_t)v1.w << 32) | v1.z, NP) << shift;
+            const gptr<const u32x4> sp = src + (size_t)pg * (N / 2);
+#pragma unroll
+            for (int k = 0; k < kGatherPasses; ++k) {
+                const int sb = c0 + k * kGatherPass + 4 * lane;
+                if (sb < N) {
+                    const u32x4 v0 = sp[sb / 2], v1 = sp[sb / 2 + 1];
+                    S[k][0] |= net_compress(((uint64_t)v0.y << 32) | v0.x, NP) << shift;
+                    S[k][1] |= net_compress(((uint64_t)v0.w << 32) | v0.z, NP) << shift;
+                    S[k][2] |= net_compress(((uint64_t)v1.y << 32) | v1.x, NP) << shift;
+                    S[k][3] |= net_compress(((uint64_t)v1.w << 32) | v1.z, NP) << shift;
+                }
             }
             shift += __popcll(P);
         }
-        if (in) {
-            uint64_t o[4];
-            gather_emit(S, ND, F, o);
-            dst[sb / 2] = u32x4{(uint32_t)o[0], (uint32_t)(o[0] >> 32), (uint32_t)o[1],
-                                (uint32_t)(o[1] >> 32)};
-            dst[sb / 2 + 1] = u32x4{(uint32_t)o[2], (uint32_t)(o[2] >> 32), (uint32_t)o[3],
-                                    (uint32_t)(o[3] >> 32)};
+#pragma unroll
+        for (int k = 0; k < kGatherPasses; ++k) {
+            const int sb = c0 + k * kGatherPass + 4 * lane;
+            if (sb < N) {
+                uint64_t o[4];
+                gather_emit(S[k], ND, F, o);
+                dst[sb / 2] = u32x4{(uint32_t)o[0], (uint32_t)(o[0] >> 32), (uint32_t)o[1],
+                                    (uint32_t)(o[1] >> 32)};
+                dst[sb / 2 + 1] = u32x4{(uint32_t)o[2], (uint32_t)(o[2] >> 32), (uint32_t)o[3],
+                                        (uint32_t)(o[3] >> 32)};
+            }
         }
     }
 }
