@@ -911,30 +911,37 @@ __device__ __forceinline__ void plane_pair(Lanes *s, const uint32_t *el, const u
 }
 
 // Ties after the planes: the lanes whose top six uniform bits equal their
-// threshold's take fresh low 26 bits, four per Philox call, in ascending lane
-// order (call q = kTagTie | k, output word k & 3 for the k-th tie).  One such
-// comparison decides a tie: u < T iff low26(u) < low26(T).
+// threshold's take fresh low 26 bits (the top 26 bits of a Philox output
+// word), four per call, in ascending lane order (call kTagTie | (k >> 2),
+// output word k & 3 for the k-th tie).  One such comparison decides a tie:
+// u < T iff low26(u) < low26(T).
 constexpr uint32_t kPlanePairs = 3;            // Philox calls of bit planes: the top six bits
 constexpr uint32_t kTagTie = kTagSweep | 0x100u;
-constexpr uint32_t kLow26 = (1u << 26) - 1u;
 
-__device__ __forceinline__ void tie_one(uint64_t &und, uint64_t eq1, uint32_t L4, uint32_t L8,
+// S4 = T4 << 6, S8 = T8 << 6 (32-bit): low26(u) < low26(T) iff (u >> 6) < low26(T)
+// iff u < low26(T) << 6, so the tie's fresh word is compared as it is.
+__device__ __forceinline__ void tie_one(uint64_t &und, uint64_t eq1, uint32_t S4, uint32_t S8,
                                         uint32_t v, uint64_t &flip) {
     const uint64_t bit = und & (0ull - und);  // lowest tied lane; 0 when none is left
     und ^= bit;
-    const uint32_t t = (eq1 & bit) ? L4 : L8;
-    flip |= ((v >> 6) < t) ? bit : 0ull;
+    // the lanes this slot would accept: class dE = 4 (eq1) if v < S4, dE = 8 if v < S8
+    const uint32_t m4 = v < S4 ? ~0u : 0u, m8 = v < S8 ? ~0u : 0u;
+    const uint32_t ahi = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(eq1 >> 32), m4, m8, 0xCA);
+    const uint32_t alo = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)eq1, m4, m8, 0xCA);
+    flip = ((uint64_t)(uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(flip >> 32), (uint32_t)(bit >> 32),
+                                                             ahi, 0xF8) << 32) |
+           (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)flip, (uint32_t)bit, alo, 0xF8);  // flip | (bit & a)
 }
 
 // most tied words have one tie: the later slots are skipped once none is left
-__device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t L4, uint32_t L8,
+__device__ __forceinline__ void tie_call(uint64_t &und, uint64_t eq1, uint32_t S4, uint32_t S8,
                                          const U4 &x, uint64_t &flip) {
-    tie_one(und, eq1, L4, L8, x.x, flip);
+    tie_one(und, eq1, S4, S8, x.x, flip);
     if (und == 0) return;
-    tie_one(und, eq1, L4, L8, x.y, flip);
+    tie_one(und, eq1, S4, S8, x.y, flip);
     if (und == 0) return;
-    tie_one(und, eq1, L4, L8, x.z, flip);
-    tie_one(und, eq1, L4, L8, x.w, flip);
+    tie_one(und, eq1, S4, S8, x.z, flip);
+    tie_one(und, eq1, S4, S8, x.w, flip);
 }
 
 // The whole comparison of one word (64 replicas of one site) in one lane.  With
@@ -977,7 +984,7 @@ __device__ __forceinline__ uint64_t metropolis_word(uint64_t a1, uint64_t a2, ui
     uint32_t q = 0;
     for (; und != 0; ++q) {
         const U4 x = philox(k0, k1, w, g, h, kTagTie | q);
-        tie_call(und, eq1, T4 & kLow26, T8 & kLow26, x, flip);
+        tie_call(und, eq1, T4 << 6, T8 << 6, x, flip);
     }
     *calls += q;  // read only when counting
     return flip;
@@ -1042,7 +1049,7 @@ __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const
 #pragma unroll
         for (int k = 0; k < K; ++k) x[k] = philox(k0, k1, w[k], g[k], h, kTagTie | q);
 #pragma unroll
-        for (int k = 0; k < K; ++k) tie_call(und[k], eq1[k], T4 & kLow26, T8 & kLow26, x[k], flip[k]);
+        for (int k = 0; k < K; ++k) tie_call(und[k], eq1[k], T4 << 6, T8 << 6, x[k], flip[k]);
     }
 }
 
