@@ -44,6 +44,25 @@ __device__ inline int64_t block_sum_i64(int64_t v, int64_t *sh) {
     __syncthreads();
     return t;  // valid in thread 0
 }
+// K sums at once (one pass of barriers): v[k] <- block sum of v[k], valid in
+// thread 0; sh holds K values per wavefront of the block.
+template <int K>
+__device__ inline void block_sum_i64v(int64_t (&v)[K], int64_t *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_i64(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) sh[wave * K + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < K; ++k) {
+            int64_t t = 0;
+            for (int w = 0; w < nw; ++w) t += sh[w * K + k];
+            v[k] = t;
+        }
+    }
+    __syncthreads();
+}
 __device__ inline double block_sum_f64(double v, double *sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     v = wave_sum_f64(v);

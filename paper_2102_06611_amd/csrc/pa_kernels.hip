@@ -295,12 +295,6 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
 // part[b * 8 + k]; the next kernel derives block bases and totals by summing
 // those partials itself (no cross-block fences).
 
-// Sum of part[k * 8 + field] over k in [0, n) by the whole block (fixed order).
-__device__ int64_t block_sum_partials(const RunDesc &rd, int field, int n, int64_t *sh) {
-    int64_t s = 0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) s += rd.part[k * 8 + field];
-    return block_sum_i64(s, sh);
-}
 
 // Nearest-integer rule (Eq. resampling-factors, strict "<"): with
 // Z = ceil(2^32 tau_hat) and the parent's uniform u32 (RESAMPLE stream),
@@ -336,11 +330,11 @@ __global__ void __launch_bounds__(256) k_counts_nearest(const RunDesc *runs, Wor
             }
         }
     }
-    const int64_t bs = block_sum_i64(s, sh);
-    const int64_t bs2 = block_sum_i64(s2, sh);
+    int64_t v[2] = {s, s2};
+    block_sum_i64v(v, sh);
     if (threadIdx.x == 0) {
-        rd.part[b * 8 + 0] = bs;
-        rd.part[b * 8 + 1] = bs2;
+        rd.part[b * 8 + 0] = v[0];
+        rd.part[b * 8 + 1] = v[1];
     }
 }
 
@@ -374,13 +368,19 @@ __global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap 
     if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
     __shared__ int64_t sh[32];
     const int Rp = st->R_cur;
-    const uint64_t base = (uint64_t)block_sum_partials(rd, 3, b, sh);
-    if (b == 0) {
-        const uint64_t W = (uint64_t)block_sum_partials(rd, 3, rd.nblk, sh);
-        if (threadIdx.x == 0) st->w_total = W;
+    // the weights of the blocks before this one, and of all blocks, in one pass
+    int64_t v[2] = {0, 0};
+    for (int k = threadIdx.x; k < rd.nblk; k += blockDim.x) {
+        const int64_t q = rd.part[k * 8 + 3];
+        v[0] += k < b ? q : 0;
+        v[1] += q;
     }
+    block_sum_i64v(v, sh);
     __shared__ uint64_t base_sh;
-    if (threadIdx.x == 0) base_sh = base;
+    if (threadIdx.x == 0) {
+        base_sh = (uint64_t)v[0];
+        if (b == 0) st->w_total = (uint64_t)v[1];
+    }
     __syncthreads();
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
     uint64_t q[4] = {0, 0, 0, 0};
@@ -455,11 +455,11 @@ __global__ void __launch_bounds__(256) k_count_partials(const RunDesc *runs, Wor
         s += c;
         s2 += c * c;
     }
-    const int64_t bs = block_sum_i64(s, sh);
-    const int64_t bs2 = block_sum_i64(s2, sh);
+    int64_t v[2] = {s, s2};
+    block_sum_i64v(v, sh);
     if (threadIdx.x == 0) {
-        rd.part[b * 8 + 0] = bs;
-        rd.part[b * 8 + 1] = bs2;
+        rd.part[b * 8 + 0] = v[0];
+        rd.part[b * 8 + 1] = v[1];
     }
 }
 
@@ -475,11 +475,18 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
     __shared__ int64_t sh[32];
     __shared__ int64_t base_sh;
     const int Rp = st->R_cur;
-    const int64_t base = block_sum_partials(rd, 0, b, sh);
-    if (threadIdx.x == 0) base_sh = base;
+    // children of the blocks before this one; all children and sum r_j^2 (one pass)
+    int64_t v[3] = {0, 0, 0};
+    for (int k = threadIdx.x; k < rd.nblk; k += blockDim.x) {
+        const int64_t r = rd.part[k * 8 + 0];
+        v[0] += k < b ? r : 0;
+        v[1] += r;
+        v[2] += rd.part[k * 8 + 1];
+    }
+    block_sum_i64v(v, sh);
+    if (threadIdx.x == 0) base_sh = v[0];
     if (b == 0) {
-        const int64_t total = block_sum_partials(rd, 0, rd.nblk, sh);
-        const int64_t sq = block_sum_partials(rd, 1, rd.nblk, sh);
+        const int64_t total = v[1], sq = v[2];
         if (threadIdx.x == 0) {
             if (total > rd.C) {
                 st->err = PA_ERR_CAPACITY;
@@ -1571,15 +1578,22 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     const RunDesc &rd = runs[blockIdx.x];
     RunState *st = rd.st;
     if (st->err) return;
-    __shared__ int64_t sh[32];
+    __shared__ int64_t sh[16 * 6];
     __shared__ double shd[32];
     const int Rn = st->R_new, nb = st->cur ^ 1;
     const int nblk = (Rn + kSlotBlock - 1) / kSlotBlock;
     // runs that cross block boundaries: every block in which such a run ends
     // walks back over the blocks it spans (each lies wholly inside the run)
     // to the block where it started, and adds its length
-    int64_t fx = 0, s2x = 0;
-    double clx = 0.0;
+    // T[0..5]: the partial fields; families, sum len^2 and sum len ln len also
+    // take the crossing runs (one pass)
+    int64_t T[6] = {0, 0, 0, 0, 0, 0};
+    double c = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) T[q] += rd.part[k * 8 + q];
+        c += rd.partd[k * 2];
+    }
     for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
         const int64_t e0 = rd.part[k * 8 + 6];
         const bool cp = (e0 & kRunContPrev) != 0, cn = (e0 & kRunContNext) != 0;
@@ -1595,16 +1609,11 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
                 break;
             }
         }
-        fx += 1;
-        s2x += len * len;
-        clx += (double)len * log((double)len);
+        T[4] += 1;
+        T[5] += len * len;
+        c += (double)len * log((double)len);
     }
-    int64_t T[6];
-    for (int q = 0; q < 6; ++q) T[q] = block_sum_partials(rd, q, nblk, sh);
-    T[4] += block_sum_i64(fx, sh);
-    T[5] += block_sum_i64(s2x, sh);
-    double c = clx;
-    for (int k = threadIdx.x; k < nblk; k += blockDim.x) c += rd.partd[k * 2];
+    block_sum_i64v(T, sh);
     const double TCL = block_sum_f64(c, shd);
     if (threadIdx.x != 0) return;
     const int step = st->step + 1;

@@ -160,8 +160,9 @@ __device__ void features_block(const RunDesc &rd, float *feat) {
         s1 += n * e;
         s2 += n * e * e;
     }
-    const int64_t S1 = block_sum_i64(s1, sh);
-    const int64_t S2 = block_sum_i64(s2, sh);
+    int64_t S[2] = {s1, s2};
+    block_sum_i64v(S, sh);
+    const int64_t S1 = S[0], S2 = S[1];
     if (threadIdx.x < 32) bins[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         const __int128 var = (__int128)R * S2 - (__int128)S1 * S1;  // R^2 Var(E)
