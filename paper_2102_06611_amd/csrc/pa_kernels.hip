@@ -85,15 +85,18 @@ __global__ void k_init_population(const RunDesc *runs, WorkMap map) {
 // memory, otherwise each slot adds to the global histogram directly.
 constexpr int kLdsBins = 4096;
 
-__device__ void block_histogram(const RunDesc &rd, RunState *st, int j0, int j1) {
+// lev[m]: levels of the block's slots held by this thread (-1: none)
+template <int M>
+__device__ void block_histogram(const RunDesc &rd, RunState *st, const int (&lev)[M]) {
     __shared__ int32_t bins[kLdsBins];
     __shared__ int32_t rng[2];
-    const int N = rd.N;
     int kmin = INT_MAX, kmax = -1;
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
-        const int k = (rd.E[j] + 2 * N) >> 2;
-        kmin = min(kmin, k);
-        kmax = max(kmax, k);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (lev[m] >= 0) {
+            kmin = min(kmin, lev[m]);
+            kmax = max(kmax, lev[m]);
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -118,14 +121,16 @@ __device__ void block_histogram(const RunDesc &rd, RunState *st, int j0, int j1)
     }
     const int span = hi - lo + 1;
     if (span > kLdsBins) {
-        for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x)
-            atomicAdd(&rd.hist[(rd.E[j] + 2 * N) >> 2], 1);
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (lev[m] >= 0) atomicAdd(&rd.hist[lev[m]], 1);
         return;
     }
     for (int k = threadIdx.x; k < span; k += blockDim.x) bins[k] = 0;
     __syncthreads();
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x)
-        atomicAdd(&bins[((rd.E[j] + 2 * N) >> 2) - lo], 1);
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        if (lev[m] >= 0) atomicAdd(&bins[lev[m] - lo], 1);
     __syncthreads();
     for (int k = threadIdx.x; k < span; k += blockDim.x)
         if (bins[k]) atomicAdd(&rd.hist[lo + k], bins[k]);
@@ -146,8 +151,14 @@ __global__ void __launch_bounds__(256) k_hist(const RunDesc *runs, WorkMap map) 
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
-    const int Rc = st->R_cur;
-    block_histogram(rd, st, b * kSlotBlock, min((b + 1) * kSlotBlock, Rc));
+    const int Rc = st->R_cur, j1 = min((b + 1) * kSlotBlock, Rc);
+    int lev[kSlotBlock / 256];
+#pragma unroll
+    for (int m = 0; m < kSlotBlock / 256; ++m) {
+        const int j = b * kSlotBlock + m * 256 + (int)threadIdx.x;
+        lev[m] = j < j1 ? (rd.E[j] + 2 * rd.N) >> 2 : -1;
+    }
+    block_histogram(rd, st, lev);
 }
 
 // ------------------------------------------------------------------ normalisation
@@ -430,8 +441,17 @@ __global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap
             const int mid = (cl + ch) >> 1;
             if (coarse[mid] > target) ch = mid; else cl = mid + 1;
         }
-        lo = 64 * cl;
-        hi = min(64 * cl + 63, Rp - 1);
+        // within the stretch (its last weight exceeds target): the eighths, then
+        // the parents of one eighth, each by eight independent loads
+        const int s0 = 64 * cl, last = min(64 * cl + 63, Rp - 1);
+        int e = 0;  // eighths whose last weight is <= target
+#pragma unroll
+        for (int k = 0; k < 7; ++k) e += cum[min(s0 + 8 * k + 7, last)] <= target ? 1 : 0;
+        const int b0 = s0 + 8 * e;
+        int f = 0;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) f += cum[min(b0 + k, last)] <= target ? 1 : 0;
+        lo = hi = b0 + f;
     }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -475,6 +495,11 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
     __shared__ int64_t sh[32];
     __shared__ int64_t base_sh;
     const int Rp = st->R_cur;
+    // this thread's four counts (loaded first: they do not depend on the sums)
+    const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
+    int c[4] = {0, 0, 0, 0};
+    for (int m = 0; m < 4; ++m)
+        if (j + m < Rp) c[m] = rd.cnt[j + m];
     // children of the blocks before this one; all children and sum r_j^2 (one pass)
     int64_t v[3] = {0, 0, 0};
     for (int k = threadIdx.x; k < rd.nblk; k += blockDim.x) {
@@ -503,10 +528,6 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
     for (int k = b * (int)blockDim.x + (int)threadIdx.x; k < rd.K; k += rd.nblk * (int)blockDim.x)
         rd.hist[k] = 0;
     __syncthreads();
-    const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
-    int c[4] = {0, 0, 0, 0};
-    for (int m = 0; m < 4; ++m)
-        if (j + m < Rp) c[m] = rd.cnt[j + m];
     int64_t tot;
     int64_t run = base_sh + block_exclusive_scan(c[0] + c[1] + c[2] + c[3], sh, &tot);
     for (int m = 0; m < 4; ++m) {
@@ -1521,12 +1542,14 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     int64_t sE = 0, sE2 = 0, sM = 0, sM2 = 0, f = 0, s2 = 0;
     double cl = 0.0;
     int run_start = prev;
+    int lev[4] = {-1, -1, -1, -1};  // energy levels of the slots, for the histogram
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int c = c0 + m;
         if (c >= j1) break;
         if (is_start[m]) run_start = c;
         const int64_t e = rd.E[c], mm = rd.M[c];
+        lev[m] = (int)((e + 2 * rd.N) >> 2);
         sE += e;
         sE2 += e * e;
         sM += mm < 0 ? -mm : mm;
@@ -1568,7 +1591,7 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
         rd.part[b * 8 + 6] = edge[0] | (cont_next ? kRunContNext : 0) | (cont_prev ? kRunContPrev : 0);
         rd.part[b * 8 + 7] = edge[1];
     }
-    block_histogram(rd, st, j0, j1);
+    block_histogram(rd, st, lev);
 }
 
 // One block per run: combine the partials of k_reduce, write record i (Sec.
