@@ -75,19 +75,26 @@ def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial"
     wall = time.perf_counter() - t0
     recs = [run.observables(i) for i in range(K + 1)]
     attempts = sum(r["R_i"] for r in recs[1:]) * L * L * THETA
-    # the same K steps again with phase timing and Philox-call counting (the
-    # run is deterministic: same populations, same calls)
-    prun = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream)
-    autotune.apply(prun, L, R, layout)
-    prun.profile(True)
-    for _ in range(K):
-        prun.anneal_step()
-    prun.sync()
-    prof = prun.profile_read()
-    last = prun.observables(K)
-    if (last["R_i"], last["minus_beta_F"]) != (recs[K]["R_i"], recs[K]["minus_beta_F"]):
-        raise RuntimeError("the profiled run differs from the timed run")
-    prun.close()
+    # the same K steps again with phase timing, then once more counting the
+    # Philox calls (counting slows the sweeps; the runs are deterministic:
+    # same populations, same calls)
+    prof = None
+    for count in (False, True):
+        prun = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream)
+        autotune.apply(prun, L, R, layout)
+        prun.profile(True, count_calls=count)
+        for _ in range(K):
+            prun.anneal_step()
+        prun.sync()
+        p = prun.profile_read()
+        last = prun.observables(K)
+        if (last["R_i"], last["minus_beta_F"]) != (recs[K]["R_i"], recs[K]["minus_beta_F"]):
+            raise RuntimeError("the profiled run differs from the timed run")
+        prun.close()
+        if prof is None:
+            prof = p
+        else:
+            prof["philox_calls"], prof["sweep_words"] = p["philox_calls"], p["sweep_words"]
     prof["geometry"] = list(geometry)
     return run, wall, prof, recs, attempts
 

@@ -178,11 +178,14 @@ pa_status pa_overlap(pa_ctx *ctx, double dbeta, double *alpha);
  * 2^-49 (dbeta_max if that already qualifies).  Synchronises. */
 pa_status pa_adaptive_dbeta(pa_ctx *ctx, double alpha_target, double dbeta_max, double *dbeta);
 
-/* Phase timing.  While enabled, every step records HIP events on the run's
- * stream before the resampling (histogram, Q_i, copy counts, offsets,
- * copy/compaction), before the sweeps, before the measurement/record kernel
- * and after it; the sweep kernel also counts the Philox4x32-10 calls it makes.
- * pa_profile(ctx, 1) resets the totals.  Asynchronous. */
+/* Phase timing.  enable = 0 turns it off; otherwise every step records HIP
+ * events on the run's stream before the resampling (histogram, Q_i, copy
+ * counts, offsets, copy/compaction), before the sweeps, before the
+ * measurement/record kernel and after it; with the value 2 set in enable
+ * the sweep kernel also counts the Philox4x32-10 calls its words need and the
+ * words it updates (this costs the sweeps a few per cent: time with
+ * enable = 1, count with enable = 3).  A nonzero enable resets the totals;
+ * any other bit set: PA_ERR_ARG.  Asynchronous. */
 pa_status pa_profile(pa_ctx *ctx, int32_t enable);
 
 /* Totals since profiling was enabled: steps timed, summed milliseconds of the

@@ -281,8 +281,8 @@ class Run:
                                          ctypes.byref(v)), self.h)
         return t.value, g.value, v.value
 
-    def profile(self, enable: bool = True):
-        _check(lib().pa_profile(self.h, 1 if enable else 0), self.h)
+    def profile(self, enable: bool = True, count_calls: bool = False):
+        _check(lib().pa_profile(self.h, (1 | (2 if count_calls else 0)) if enable else 0), self.h)
 
     def profile_read(self) -> dict:
         n = ctypes.c_int32()

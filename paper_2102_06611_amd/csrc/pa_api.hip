@@ -820,10 +820,11 @@ pa_status pa_profile(pa_ctx *ctx, int32_t enable) {
     pa_batch *B = &ctx->b;
     if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
     PA_HIP(B, hipStreamSynchronize(B->stream));
+    if (enable & ~3) return fail(B, PA_ERR_ARG, "enable must be a combination of 1 and 2");
     B->profiling = enable != 0;
     if (B->profiling) B->profiled_steps = 0;
     for (int r = 0; r < B->n; ++r) {
-        const int32_t on = B->profiling ? 1 : 0;
+        const int32_t on = (enable & 2) ? 1 : 0;
         PA_HIP(B, hipMemcpy(&B->desc[r].st->count_calls, &on, sizeof on, hipMemcpyHostToDevice));
         if (!B->profiling) continue;
         unsigned long long zero[2] = {0, 0};

@@ -255,6 +255,35 @@ def test_sweep_geometry_does_not_change_results(L):
     r.close()
 
 
+def test_profiling_modes():
+    """Timing alone counts nothing; counting gives the Philox calls the words
+    need (three plane calls at most, plus tie calls) and every word update;
+    neither changes the results; other enable bits are rejected."""
+    L, R, theta, n = 16, 3000, 3, 4
+    betas = linear_schedule(0.44, n)
+    ref = pa.Run(L, R, betas, theta, 63, "nearest", "msc64")
+    ref.run(n)
+    want = ref.observables(n)
+    ref.close()
+    for count in (False, True):
+        r = pa.Run(L, R, betas, theta, 63, "nearest", "msc64")
+        r.profile(True, count_calls=count)
+        r.run(n)
+        p = r.profile_read()
+        assert r.observables(n) == want
+        assert p["steps"] == n and p["ms_sweep"] > 0.0
+        if not count:
+            assert p["philox_calls"] == 0 and p["sweep_words"] == 0
+        else:
+            # step i sweeps its new population of R_i replicas: one word per site and group
+            groups = sum(math.ceil(r.observables(i)["R_i"] / 64) for i in range(1, n + 1))
+            assert p["sweep_words"] == groups * theta * L * L
+            assert 2.0 < p["philox_calls"] / p["sweep_words"] < 4.0, p
+        with pytest.raises(pa.PAError):
+            pa._check(pa.lib().pa_profile(r.h, 4), r.h)
+        r.close()
+
+
 def test_autotuner_times_candidates_and_keeps_results():
     from paper_2102_06611_amd import autotune
     betas = linear_schedule(0.44, 10)
