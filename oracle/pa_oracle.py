@@ -32,6 +32,9 @@ file takes the per-step decisions, following Sec. "Algorithm" steps 1-5:
 * Sec. "Families": f, rho_t = R_i sum n_k^2 (Eq. rhot), S_f and
   rho_s = R_i / exp(S_f) (Eq. rhos); the one-step rho_t(beta_{i-1}, beta_i)
   = R_i sum_k (r_k / R_i)^2 of Eq. (one-step-Reff).
+* Sec. "Effective population size" and Sec. "Statistical errors": blocking
+  R_eff(E), R_eff(|M|) and single-run error bars of e, m, C_V, chi over the
+  tree-ordered population (oracle/blocking.py).
 
 Every integer decision is taken on a 256-bit value and is checked to be at
 least 2^-100 away from its rounding boundary unless the value is exact.
@@ -47,6 +50,8 @@ from typing import Dict, List, Optional
 
 import mpmath
 import numpy as np
+
+from oracle import blocking
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pa_oracle.c")
@@ -233,6 +238,12 @@ class Record:
     rho_t: float
     rho_s: float
     rho_t_step: float
+    r_eff_E: float
+    r_eff_absM: float
+    err_e: float
+    err_m: float
+    err_c_v: float
+    err_chi: float
 
 
 def observables(L: int, beta: float, E: np.ndarray, M: np.ndarray):
@@ -296,8 +307,9 @@ class OracleRun:
         f, sum_c2, rho_t, rho_s = family_stats(self.fam)
         R_i = len(self.E)
         rho_step = float(Fraction(sum_cnt2, R_i)) if self.step > 0 else 0.0
+        errs = blocking.population_errors(self.L, beta, self.E, self.M)
         return Record(self.step, beta, R_i, *sums, *obs, float(ln_q), float(self._acc),
-                      f, sum_c2, int(sum_cnt2), rho_t, rho_s, rho_step)
+                      f, sum_c2, int(sum_cnt2), rho_t, rho_s, rho_step, *errs)
 
     # -- step 2 of the algorithm ------------------------------------------------
     def copy_counts(self, beta_prev: float, beta_next: float, step: int):
