@@ -101,6 +101,18 @@ typedef struct pa_obs {
     double rho_t;         /* Eq. rhot: R_i sum_k (c_k / R_i)^2 */
     double rho_s;         /* Eq. rhos: R_i / exp(S_f), S_f = -sum_k n_k ln n_k */
     double rho_t_step;    /* Eq. one-step-Reff: R_i sum_j (r_j / R_i)^2 */
+    /* Blocking over the tree-ordered population (Sec. "Effective population
+     * size", Eqs. blocks, blocked_variance, neff; Sec. "Statistical errors",
+     * Eqs. jackknife-blocks, jackknife-variance): n = min(100, R_i) blocks of
+     * consecutive slots, block k = slots [floor(k R_i / n), floor((k+1) R_i / n)).
+     * NaN when n < 2; a zero blocked variance gives R_eff = inf (NaN if the
+     * values do not vary). */
+    double r_eff_E;       /* sigma^2(E) / sigma^2(mean E), sigma^2 unbiased over the replicas */
+    double r_eff_absM;    /* the same for |M| */
+    double err_e;         /* blocked standard error of e */
+    double err_m;         /* blocked standard error of m */
+    double err_c_v;       /* jackknife standard error of c_v */
+    double err_chi;       /* jackknife standard error of chi */
 } pa_obs;
 
 typedef struct pa_ctx pa_ctx;

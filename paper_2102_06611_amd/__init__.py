@@ -50,7 +50,10 @@ class pa_obs(ctypes.Structure):
                 ("minus_beta_F", ctypes.c_double), ("n_families", ctypes.c_int64),
                 ("sum_fam2", ctypes.c_int64), ("sum_cnt2", ctypes.c_int64),
                 ("rho_t", ctypes.c_double), ("rho_s", ctypes.c_double),
-                ("rho_t_step", ctypes.c_double)]
+                ("rho_t_step", ctypes.c_double), ("r_eff_E", ctypes.c_double),
+                ("r_eff_absM", ctypes.c_double), ("err_e", ctypes.c_double),
+                ("err_m", ctypes.c_double), ("err_c_v", ctypes.c_double),
+                ("err_chi", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -60,7 +60,7 @@ bool validate(const pa_config &c, std::string *why) {
 struct RunPlan {
     int L, N, R, C, G, K, nblk, max_steps;
     size_t off_ms[2], off_s8[2], off_E, off_M, off_fam[2], off_hist, off_zlev, off_wlev,
-        off_cnt, off_off, off_par, off_cum, off_part, off_partd, off_betas, off_records, off_st,
+        off_cnt, off_off, off_par, off_cum, off_part, off_partd, off_blk, off_betas, off_records, off_st,
         off_stage, off_feat, off_flog, off_tlog, off_alog, off_alpha;
     size_t bytes;
 };
@@ -104,6 +104,7 @@ RunPlan plan_run(const pa_config &c) {
     p.off_cum = take((size_t)p.C * 8);
     p.off_part = take((size_t)p.nblk * 8 * 8);
     p.off_partd = take((size_t)p.nblk * 2 * 8);
+    p.off_blk = take((size_t)kBlocks * 4 * 8);
     p.off_betas = take((size_t)(p.max_steps + 1) * 8);
     p.off_records = take((size_t)(p.max_steps + 1) * sizeof(pa_obs));
     p.off_st = take(sizeof(RunState));
@@ -358,6 +359,7 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         d.cum = (uint64_t *)(base + p.off_cum);
         d.part = (int64_t *)(base + p.off_part);
         d.partd = (double *)(base + p.off_partd);
+        d.blk = (int64_t *)(base + p.off_blk);
         d.betas = (double *)(base + p.off_betas);
         d.records = (pa_obs *)(base + p.off_records);
         d.st = (RunState *)(base + p.off_st);

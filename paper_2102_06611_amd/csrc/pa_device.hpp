@@ -23,6 +23,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // 16-byte copies
 constexpr int kLanes = 64;        // replicas per group = bits per multispin word
 constexpr int kSlotBlock = 1024;  // replica slots per block of the per-slot kernels
 constexpr int kMaxL = 128;
+constexpr int kBlocks = 100;      // blocks of the blocking / jackknife analysis
 // dynamic LDS available to one sweep block (the static part is 4 KiB)
 constexpr int kMaxSweepLds = 152 * 1024;
 
@@ -74,6 +75,7 @@ struct RunDesc {
     int32_t *par;              // [C] parent of each child slot of the last resampling
     uint64_t *cum;             // [C] multinomial cumulative quantised weights
     int64_t *part;             // [nblk * 4] per-block partial sums
+    int64_t *blk;              // [kBlocks * 4] blocking sums of E, E^2, |M|, M^2 (zero between steps)
     double *partd;             // [nblk * 2] per-block FP partials
     double *betas;             // [max_steps + 1]
     pa_obs *records;           // [max_steps + 1]

@@ -1506,6 +1506,7 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     __shared__ double shd[4];
     __shared__ int wmax[16];
     __shared__ int64_t edge[2];
+    __shared__ int64_t bsum[kBlocks * 4];  // blocking sums of the blocks this block touches
     const int Rn = st->R_new, nb = st->cur ^ 1;
     const int32_t *fam = rd.fam[nb];
     const int j0 = b * kSlotBlock, j1 = min(j0 + kSlotBlock, Rn);
@@ -1515,6 +1516,15 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
         edge[0] = 0;
         edge[1] = 0;
     }
+    // blocking (Sec. "Effective population size", Eq. blocks): slot j lies in
+    // block floor(((j + 1) n - 1) / R_i) of n = min(kBlocks, R_i) (the quotient of
+    // two integers below 2^53, at least 1/R_i away from the next integer unless
+    // it is one, so its binary64 floor is exact); this block's slots [j0, j1)
+    // touch blocks kb0 .. kb1
+    const int nbk = min(kBlocks, Rn);
+    auto block_of = [&](int j) { return (int)floor((double)((int64_t)(j + 1) * nbk - 1) / (double)Rn); };
+    const int kb0 = j1 > j0 ? block_of(j0) : 0, kb1 = j1 > j0 ? block_of(j1 - 1) : -1;
+    for (int k = threadIdx.x; k < 4 * (kb1 - kb0 + 1); k += blockDim.x) bsum[k] = 0;
     // each thread owns 4 consecutive slots
     const int c0 = j0 + 4 * (int)threadIdx.x;
     int last_start = -1;  // start of the run containing the thread's last slot, within the thread
@@ -1543,6 +1553,7 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     double cl = 0.0;
     int run_start = prev;
     int lev[4] = {-1, -1, -1, -1};  // energy levels of the slots, for the histogram
+    int64_t ev[4] = {0, 0, 0, 0}, av[4] = {0, 0, 0, 0};  // E and |M| of the slots
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int c = c0 + m;
@@ -1550,6 +1561,8 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
         if (is_start[m]) run_start = c;
         const int64_t e = rd.E[c], mm = rd.M[c];
         lev[m] = (int)((e + 2 * rd.N) >> 2);
+        ev[m] = e;
+        av[m] = mm < 0 ? -mm : mm;
         sE += e;
         sE2 += e * e;
         sM += mm < 0 ? -mm : mm;
@@ -1567,6 +1580,27 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
                 cl += (double)len * log((double)len);
             }
         }
+    }
+    {  // the thread's slots into the LDS blocking sums (one group of adds per block met)
+        int kcur = -1;
+        int64_t t[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (lev[m] < 0) continue;
+            const int k = block_of(c0 + m);
+            if (k != kcur) {
+                if (kcur >= 0)
+                    for (int q = 0; q < 4; ++q) atomicAdd(reinterpret_cast<unsigned long long *>(&bsum[4 * (kcur - kb0) + q]), (unsigned long long)t[q]);
+                kcur = k;
+                t[0] = t[1] = t[2] = t[3] = 0;
+            }
+            t[0] += ev[m];
+            t[1] += ev[m] * ev[m];
+            t[2] += av[m];
+            t[3] += av[m] * av[m];
+        }
+        if (kcur >= 0)
+            for (int q = 0; q < 4; ++q) atomicAdd(reinterpret_cast<unsigned long long *>(&bsum[4 * (kcur - kb0) + q]), (unsigned long long)t[q]);
     }
     const int64_t v[6] = {sE, sE2, sM, sM2, f, s2};
 #pragma unroll
@@ -1591,6 +1625,9 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
         rd.part[b * 8 + 6] = edge[0] | (cont_next ? kRunContNext : 0) | (cont_prev ? kRunContPrev : 0);
         rd.part[b * 8 + 7] = edge[1];
     }
+    // the blocking sums to blk[] (integer atomics: the totals do not depend on the order)
+    for (int k = threadIdx.x; k < 4 * (kb1 - kb0 + 1); k += blockDim.x)
+        if (bsum[k]) atomicAdd(reinterpret_cast<unsigned long long *>(&rd.blk[4 * kb0 + k]), (unsigned long long)bsum[k]);
     block_histogram(rd, st, lev);
 }
 
@@ -1605,6 +1642,14 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     __shared__ double shd[32];
     const int Rn = st->R_new, nb = st->cur ^ 1;
     const int nblk = (Rn + kSlotBlock - 1) / kSlotBlock;
+    // thread k < n: the blocking sums of block k (used below), cleared for the next step
+    const int nbk = min(kBlocks, Rn);
+    const bool own = (int)threadIdx.x < nbk;
+    int64_t bs[4] = {0, 0, 0, 0};
+    if (own) {
+        for (int q = 0; q < 4; ++q) bs[q] = rd.blk[4 * threadIdx.x + q];
+        for (int q = 0; q < 4; ++q) rd.blk[4 * threadIdx.x + q] = 0;
+    }
     // runs that cross block boundaries: every block in which such a run ends
     // walks back over the blocks it spans (each lies wholly inside the run)
     // to the block where it started, and adds its length
@@ -1638,15 +1683,55 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     }
     block_sum_i64v(T, sh);
     const double TCL = block_sum_f64(c, shd);
-    if (threadIdx.x != 0) return;
     const int step = st->step + 1;
     const double beta = rd.betas[step];
+    const double Nd = (double)rd.N;
+
+    // blocking and jackknife (Sec. "Effective population size", Eqs. blocks,
+    // blocked_variance, neff, jackknife-blocks, jackknife-variance; Sec.
+    // "Statistical errors"): thread k < n holds block k's sums (loaded above): its
+    // means of E and |M|, and c_v and chi of the jackknife sample without block k,
+    // whose variances n_k^2 Var come from exact integers (n_k = R_i - B_k
+    // replicas).  Each enters as its difference d from the value of the whole
+    // population, so that sum (x - mean x)^2 = sum d^2 - (sum d)^2 / n is formed
+    // from small numbers in one pass.
+    __shared__ int64_t tot_sh[4];
+    __shared__ double bsh[16 * 8];
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) tot_sh[q] = T[q];
+    __syncthreads();
+    const double Rd = (double)Rn;
+    const double whole[4] = {
+        (double)tot_sh[0] / Rd, (double)tot_sh[2] / Rd,
+        beta * beta / Nd * ((double)((__int128)Rn * tot_sh[1] - (__int128)tot_sh[0] * tot_sh[0]) / (Rd * Rd)),
+        beta / Nd * ((double)((__int128)Rn * tot_sh[3] - (__int128)tot_sh[2] * tot_sh[2]) / (Rd * Rd))};
+    double dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sum d, sum d^2 for E, |M|, c_v, chi
+    if (own) {
+        const int k = threadIdx.x;
+        const int64_t Bk = (int64_t)(k + 1) * Rn / nbk - (int64_t)k * Rn / nbk, nk = Rn - Bk;
+        const int64_t r1 = tot_sh[0] - bs[0], r2 = tot_sh[1] - bs[1];
+        const int64_t q1 = tot_sh[2] - bs[2], q2 = tot_sh[3] - bs[3];
+        const double nk2 = (double)nk * (double)nk;
+        const double x[4] = {
+            (double)bs[0] / (double)Bk, (double)bs[2] / (double)Bk,
+            beta * beta / Nd * ((double)((__int128)nk * r2 - (__int128)r1 * r1) / nk2),
+            beta / Nd * ((double)((__int128)nk * q2 - (__int128)q1 * q1) / nk2)};
+        for (int q = 0; q < 4; ++q) {
+            const double d = x[q] - whole[q];
+            dv[2 * q] = d;
+            dv[2 * q + 1] = d * d;
+        }
+    }
+    block_sum_f64v(dv, bsh);  // thread 0
+    double ss[4];             // sums of squared deviations from the means over the n blocks
+    for (int q = 0; q < 4; ++q) ss[q] = dv[2 * q + 1] - dv[2 * q] * dv[2 * q] / nbk;
+    if (threadIdx.x != 0) return;
     if (step > 0) {  // -beta_i F_i = -beta_{i-1} F_{i-1} + ln Q_i, now that step i is complete
         dd acc = dd_add(dd{st->acc_hi, st->acc_lo}, dd{st->lnq_hi, st->lnq_lo});
         st->acc_hi = acc.hi;
         st->acc_lo = acc.lo;
     }
-    const double N = (double)rd.N, R = (double)Rn;
+    const double N = Nd, R = (double)Rn;
     pa_obs o;
     o.step = step;
     o.R_i = Rn;
@@ -1669,6 +1754,19 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     o.rho_t = (double)T[5] / R;
     o.rho_s = exp(TCL / R);
     o.rho_t_step = step == 0 ? 0.0 : (double)st->sum_cnt2 / R;
+    if (nbk < 2) {
+        o.r_eff_E = o.r_eff_absM = o.err_e = o.err_m = o.err_c_v = o.err_chi = __builtin_nan("");
+    } else {
+        const double nn = (double)nbk * (double)(nbk - 1), jf = (double)(nbk - 1) / (double)nbk;
+        const double vE = ss[0] / nn, vM = ss[1] / nn;  // blocked variances of the means
+        const double rr = R * (R - 1.0);
+        o.r_eff_E = ((double)varE / rr) / vE;
+        o.r_eff_absM = ((double)varM / rr) / vM;
+        o.err_e = sqrt(vE) / N;
+        o.err_m = sqrt(vM) / N;
+        o.err_c_v = sqrt(jf * ss[2]);
+        o.err_chi = sqrt(jf * ss[3]);
+    }
     rd.records[step] = o;
     st->r_parents = step == 0 ? 0 : st->R_cur;
     st->step = step;
