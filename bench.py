@@ -242,6 +242,7 @@ def main():
             "copy_hbm_gbs": copy_bytes / (copy_ms * 1e-3) / 1e9,
             "beta_f_error_per_spin": {"at_last_step": err[-1], "max": max(err)},
             "beta_last": recs[-1]["beta"],
+            "blocking_last": {k: recs[-1][k] for k in ("r_eff_E", "r_eff_absM", "err_e")},
             "sweep_geometry": prof["geometry"],
         }
         if layout == head_candidate(args.layouts) and not args.no_cpu_baseline:

@@ -63,23 +63,6 @@ __device__ inline void block_sum_i64v(int64_t (&v)[K], int64_t *sh) {
     }
     __syncthreads();
 }
-template <int K>
-__device__ inline void block_sum_f64v(double (&v)[K], double *sh) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum_f64(v[k]);
-    if (lane == 0)
-        for (int k = 0; k < K; ++k) sh[wave * K + k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < K; ++k) {
-            double t = 0;
-            for (int w = 0; w < nw; ++w) t += sh[w * K + k];
-            v[k] = t;
-        }
-    }
-    __syncthreads();
-}
 __device__ inline double block_sum_f64(double v, double *sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     v = wave_sum_f64(v);

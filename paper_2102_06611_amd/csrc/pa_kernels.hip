@@ -1645,10 +1645,11 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     // thread k < n: the blocking sums of block k (used below), cleared for the next step
     const int nbk = min(kBlocks, Rn);
     const bool own = (int)threadIdx.x < nbk;
-    int64_t bs[4] = {0, 0, 0, 0};
+    int64_t bs[4] = {0, 0, 0, 0}, Bk = 0;
     if (own) {
         for (int q = 0; q < 4; ++q) bs[q] = rd.blk[4 * threadIdx.x + q];
         for (int q = 0; q < 4; ++q) rd.blk[4 * threadIdx.x + q] = 0;
+        Bk = (int64_t)(threadIdx.x + 1) * Rn / nbk - (int64_t)threadIdx.x * Rn / nbk;
     }
     // runs that cross block boundaries: every block in which such a run ends
     // walks back over the blocks it spans (each lies wholly inside the run)
@@ -1696,7 +1697,7 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     // population, so that sum (x - mean x)^2 = sum d^2 - (sum d)^2 / n is formed
     // from small numbers in one pass.
     __shared__ int64_t tot_sh[4];
-    __shared__ double bsh[16 * 8];
+    __shared__ double bdev[kBlocks][8], dsum[8];
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) tot_sh[q] = T[q];
     __syncthreads();
@@ -1705,10 +1706,9 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
         (double)tot_sh[0] / Rd, (double)tot_sh[2] / Rd,
         beta * beta / Nd * ((double)((__int128)Rn * tot_sh[1] - (__int128)tot_sh[0] * tot_sh[0]) / (Rd * Rd)),
         beta / Nd * ((double)((__int128)Rn * tot_sh[3] - (__int128)tot_sh[2] * tot_sh[2]) / (Rd * Rd))};
-    double dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sum d, sum d^2 for E, |M|, c_v, chi
-    if (own) {
+    if (own) {  // d and d^2 for E, |M|, c_v, chi
         const int k = threadIdx.x;
-        const int64_t Bk = (int64_t)(k + 1) * Rn / nbk - (int64_t)k * Rn / nbk, nk = Rn - Bk;
+        const int64_t nk = Rn - Bk;
         const int64_t r1 = tot_sh[0] - bs[0], r2 = tot_sh[1] - bs[1];
         const int64_t q1 = tot_sh[2] - bs[2], q2 = tot_sh[3] - bs[3];
         const double nk2 = (double)nk * (double)nk;
@@ -1718,13 +1718,19 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
             beta / Nd * ((double)((__int128)nk * q2 - (__int128)q1 * q1) / nk2)};
         for (int q = 0; q < 4; ++q) {
             const double d = x[q] - whole[q];
-            dv[2 * q] = d;
-            dv[2 * q + 1] = d * d;
+            bdev[k][2 * q] = d;
+            bdev[k][2 * q + 1] = d * d;
         }
     }
-    block_sum_f64v(dv, bsh);  // thread 0
-    double ss[4];             // sums of squared deviations from the means over the n blocks
-    for (int q = 0; q < 4; ++q) ss[q] = dv[2 * q + 1] - dv[2 * q] * dv[2 * q] / nbk;
+    __syncthreads();
+    if (threadIdx.x < 8) {  // eight sums over the blocks, each in block order
+        double t = 0.0;
+        for (int k = 0; k < nbk; ++k) t += bdev[k][threadIdx.x];
+        dsum[threadIdx.x] = t;
+    }
+    __syncthreads();
+    double ss[4];  // sums of squared deviations from the means over the n blocks
+    for (int q = 0; q < 4; ++q) ss[q] = dsum[2 * q + 1] - dsum[2 * q] * dsum[2 * q] / nbk;
     if (threadIdx.x != 0) return;
     if (step > 0) {  // -beta_i F_i = -beta_{i-1} F_{i-1} + ln Q_i, now that step i is complete
         dd acc = dd_add(dd{st->acc_hi, st->acc_lo}, dd{st->lnq_hi, st->lnq_lo});

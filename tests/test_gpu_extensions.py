@@ -284,6 +284,22 @@ def test_profiling_modes():
         r.close()
 
 
+def test_effective_population_size_is_bounded_below_by_the_families():
+    """Sec. "Effective population size": R / rho_t from the family statistics is
+    a lower bound of the blocking estimate R_eff(E) (far from tight).  The
+    blocked variance is itself an estimate (99 degrees of freedom), hence the
+    factor 1/2; at beta = 0 the population is uncorrelated and R_eff is about R."""
+    L, R, theta, n = 16, 20000, 5, 30
+    r = pa.Run(L, R, linear_schedule(0.44, n), theta, 64, "nearest", "msc64")
+    r.run(n)
+    recs = [r.observables(i) for i in range(n + 1)]
+    r.close()
+    assert 0.6 * R < recs[0]["r_eff_E"] < 1.6 * R
+    for o in recs[1:]:
+        assert o["r_eff_E"] > 0.5 * o["R_i"] / o["rho_t"], o
+        assert o["err_e"] > 0.0 and o["err_c_v"] > 0.0
+
+
 def test_autotuner_times_candidates_and_keeps_results():
     from paper_2102_06611_amd import autotune
     betas = linear_schedule(0.44, 10)
