@@ -80,6 +80,7 @@ void oracle_philox4x32_10(uint32_t key0, uint32_t key1, const uint32_t ctr[4], u
 #define TAG_INIT 0x20000000u
 #define TAG_RESAMPLE 0x30000000u
 #define TAG_MULTI 0x40000000u
+#define TAG_POISSON 0x50000000u
 
 static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t out[4]) {
     uint32_t ctr[4] = {c0, c1, c2, c3};
@@ -138,6 +139,15 @@ uint64_t oracle_multinomial_uniform(uint64_t seed, uint32_t step, uint32_t d) {
     uint32_t x[4];
     draw(seed, d >> 1, step, 0, TAG_MULTI, x);
     if ((d & 1u) == 0)
+        return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    return (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+}
+
+/* The 64-bit uniform of parent j for Poisson resampling at step i. */
+uint64_t oracle_poisson_uniform(uint64_t seed, uint32_t step, uint32_t j) {
+    uint32_t x[4];
+    draw(seed, j >> 1, step, 0, TAG_POISSON, x);
+    if ((j & 1u) == 0)
         return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
     return (uint64_t)x[2] | ((uint64_t)x[3] << 32);
 }

@@ -18,6 +18,9 @@ file takes the per-step decisions, following Sec. "Algorithm" steps 1-5:
   floor(tau_hat) + 1 when u < tau_hat - floor(tau_hat) and floor(tau_hat)
   otherwise, u = u32 / 2^32 the parent's resampling uniform (strict "<": the
   reading taken where the paper's "r > frac" leaves r = frac to the "+1" side).
+* Poisson resampling (Sec. "Algorithm", fluctuating population size): parent
+  j makes r_j ~ Poisson(tau_hat_j) copies, drawn by inversion of a 64-bit
+  uniform U (the smallest k with U < 2^64 F(k), F the Poisson CDF).
 * Multinomial resampling (Sec. "Algorithm", fixed population size): R draws
   with probability proportional to tau_i(E_j); each weight relative to the
   largest one, exp[-dbeta (E_j - E_min)], is quantised to floor(2^40 x) and a
@@ -94,6 +97,8 @@ def lib():
         L.oracle_resample_uniform.restype = u32
         L.oracle_multinomial_uniform.argtypes = [u64, u32, u32]
         L.oracle_multinomial_uniform.restype = u64
+        L.oracle_poisson_uniform.argtypes = [u64, u32, u32]
+        L.oracle_poisson_uniform.restype = u64
         L.oracle_init_spins.argtypes = [u64, i32, i32, p_i8]
         L.oracle_init_spins.restype = None
         L.oracle_energy_magnetisation.argtypes = [i32, i32, p_i8, p_i32, p_i32]
@@ -144,6 +149,29 @@ def resample_uniform(seed: int, step: int, j: int) -> int:
 
 def multinomial_uniform(seed: int, step: int, d: int) -> int:
     return int(lib().oracle_multinomial_uniform(seed, step, d))
+
+
+def poisson_uniform(seed: int, step: int, j: int) -> int:
+    return int(lib().oracle_poisson_uniform(seed, step, j))
+
+
+def poisson_inverse(lam, U: int) -> int:
+    """Copies for Poisson resampling by inversion: the smallest k >= 0 with
+    U < 2^64 F(k), F(k) = e^-lam sum_{m<=k} lam^m / m! (the Poisson CDF of mean
+    lam, Sec. "Algorithm"); lam is a high-precision real, U a 64-bit integer."""
+    term = mpmath.exp(-lam)
+    F = term
+    k = 0
+    while True:
+        x = mpmath.ldexp(F, 64)
+        gap = abs(x - U)
+        if gap < mpmath.ldexp(mpmath.mpf(1), 64 - 100):
+            raise OracleAmbiguity("2^64 F(%d) = %s is within 2^-100 (relative) of U" % (k, mpmath.nstr(x, 40)))
+        if U < x:
+            return k
+        k += 1
+        term = term * lam / k
+        F = F + term
 
 
 # ---------------------------------------------------------------- model
@@ -286,7 +314,7 @@ class OracleRun:
     def __init__(self, L: int, R: int, theta: int, seed: int, resample: str = "nearest",
                  betas: Optional[np.ndarray] = None):
         assert L >= 4 and L % 2 == 0
-        assert resample in ("nearest", "multinomial", "none")
+        assert resample in ("nearest", "multinomial", "poisson", "none")
         self.L, self.N, self.R, self.theta, self.seed = L, L * L, R, theta, seed
         self.resample = resample
         self.betas: List[float] = [0.0] if betas is None else [float(b) for b in betas]
@@ -325,6 +353,16 @@ class OracleRun:
             ln_q = mpmath.log(Q)
             if self.resample == "none":
                 return np.ones(Rp, dtype=np.int32), ln_q
+            if self.resample == "poisson":
+                # r_j ~ Poisson(tau_hat_j) by inversion of its 64-bit uniform (Sec.
+                # "Algorithm", following Machta: a sum of Poisson distributions)
+                counts = np.zeros(Rp, dtype=np.int32)
+                single_level = len(boltz) == 1
+                for j in range(Rp):
+                    tau = mpmath.mpf(1) if single_level else boltz[int(E[j])] / Q
+                    tau_hat = mpmath.mpf(self.R) / Rp * tau  # Eq. (taus)
+                    counts[j] = poisson_inverse(tau_hat, poisson_uniform(self.seed, step, j))
+                return counts, ln_q
             if self.resample == "nearest":
                 counts = np.zeros(Rp, dtype=np.int32)
                 single_level = len(boltz) == 1
