@@ -67,6 +67,10 @@ class OracleAmbiguity(RuntimeError):
     """A decision value sits too close to its rounding boundary to be trusted."""
 
 
+class PopulationExtinct(RuntimeError):
+    """Resampling gave every parent zero copies (possible with Poisson resampling)."""
+
+
 def build(force: bool = False) -> str:
     """Compile pa_oracle.c with gcc (no FP contraction; the core is integer-only)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -404,6 +408,8 @@ class OracleRun:
                 self.betas.append(float(beta_next))
         beta_prev, beta = self.betas[i - 1], self.betas[i]
         counts, ln_q = self.copy_counts(beta_prev, beta, i)
+        if int(counts.sum()) == 0:
+            raise PopulationExtinct("no copies at step %d" % i)
         # tree order: the copies of parent j sit at adjacent slots, parents ascending
         self.spins = np.ascontiguousarray(np.repeat(self.spins, counts, axis=0))
         self.fam = np.repeat(self.fam, counts)

@@ -70,3 +70,29 @@ def test_population_size_fluctuates_about_R():
     assert 0 < sizes.std() < 3 * math.sqrt(R)
     # the copy counts of each step add up to that step's population
     assert int(o.last_counts.sum()) == o.records[-1].R_i
+
+
+def test_extinction_exactly_when_every_draw_falls_below_exp_minus_tau():
+    # a parent makes no copy iff U_j < 2^64 e^{-tau_hat_j} (F(0) = e^{-lam});
+    # with R = 2 this happens to both parents at the first step for some
+    # seeds, and the run then stops with PopulationExtinct
+    L, R, b1 = 4, 2, 0.3
+    extinct = survived = 0
+    for seed in range(40):
+        o = po.OracleRun(L, R, 1, seed, "poisson", betas=[0.0, b1])
+        E = o.E.astype(int)
+        with mpmath.workprec(po.PREC_BITS):
+            w = [mpmath.exp(-mpmath.mpf(b1) * int(e)) for e in E]
+            tau_hat = [R * x / mpmath.fsum(w) for x in w]
+            zero = [po.poisson_uniform(seed, 1, j) < mpmath.ldexp(mpmath.exp(-t), 64)
+                    for j, t in enumerate(tau_hat)]
+        if all(zero):
+            with pytest.raises(po.PopulationExtinct):
+                o.anneal_step()
+            extinct += 1
+        else:
+            rec = o.anneal_step()
+            assert rec.R_i > 0
+            assert [c == 0 for c in o.last_counts] == zero
+            survived += 1
+    assert extinct > 0 and survived > 0
