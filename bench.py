@@ -271,6 +271,22 @@ def main():
             "final_families": recs[-1]["n_families"], "final_rho_t": recs[-1]["rho_t"]}
         run.close()
         torch.cuda.empty_cache()
+        # the other copy-count rules on the headline workload (same sweeps)
+        for rule in ("nearest", "poisson"):
+            log("timing L=64, R=100000, %s, multispin: %d steps" % (rule, K))
+            run, wall, prof, recs, attempts = time_layout(pa, torch, betas, "msc64", K, 0,
+                                                          resample=rule)
+            n = prof["steps"]
+            sizes = np.array([r["R_i"] for r in recs[1:]], dtype=np.float64)
+            err = abs(recs[-1]["minus_beta_F"] - lnz[K]) / (L * L)
+            extra["l64_%s_msc64" % rule] = {
+                "attempts_per_ns": attempts / wall / 1e9, "ms_per_step": wall * 1e3 / K,
+                "resample_us_per_step": prof["ms_resample"] / n * 1e3,
+                "copy_us_per_step": prof["ms_copy"] / n * 1e3,
+                "R_i_mean": float(sizes.mean()), "R_i_std": float(sizes.std()),
+                "beta_f_error_per_spin_at_last_step": err}
+            run.close()
+            torch.cuda.empty_cache()
         log("timing the 64-run batch: 200 steps")
         extra["batched_64_runs"] = time_batch(pa, torch, 200)
         torch.cuda.empty_cache()

@@ -50,17 +50,22 @@ enum {
     PA_ERR_ARG = -1,      /* invalid argument or configuration */
     PA_ERR_NOMEM = -2,    /* workspace smaller than pa_workspace_size() */
     PA_ERR_DEVICE = -3,   /* a HIP runtime call failed; the handle is only destroyable */
-    PA_ERR_CAPACITY = -4, /* nearest-integer resampling produced R_i > capacity */
+    PA_ERR_CAPACITY = -4, /* nearest-integer or Poisson resampling produced R_i > capacity */
     PA_ERR_DONE = -5,     /* the fixed schedule has no further temperature */
     PA_ERR_STATE = -6,    /* malformed or mismatching snapshot */
-    PA_ERR_NUMERIC = -7   /* a resampling/acceptance integer could not be decided */
+    PA_ERR_NUMERIC = -7,  /* a resampling/acceptance integer could not be decided, or a
+                             Poisson mean tau_hat_j exceeds 65536 */
+    PA_ERR_EXTINCT = -8   /* resampling gave every parent zero copies (R_i = 0) */
 };
 
 /* Copy-count rule of the resampling step (Sec. "Algorithm", step 2). */
 enum {
     PA_RESAMPLE_NEAREST = 0,     /* Eq. resampling-factors: floor(tau_hat) or +1 */
     PA_RESAMPLE_MULTINOMIAL = 1, /* R draws with probability tau_i(E_j) / R_{i-1} */
-    PA_RESAMPLE_NONE = 2         /* every replica copied once (diagnostic) */
+    PA_RESAMPLE_NONE = 2,        /* every replica copied once (diagnostic) */
+    PA_RESAMPLE_POISSON = 3      /* r_j ~ Poisson(tau_hat_j) (Eq. taus), by inversion of a
+                                    64-bit uniform: the smallest k with U < 2^64 F(k), F the
+                                    Poisson CDF; fluctuating R_i */
 };
 
 /* Device layout of the population (replica r is lane r % 64 of group r / 64). */
@@ -81,7 +86,8 @@ typedef struct pa_config {
     int32_t resample;      /* PA_RESAMPLE_* */
     int32_t layout;        /* PA_LAYOUT_* */
     int32_t capacity;      /* replica slots; 0 = default: R + ceil(10 sqrt R)
-                              rounded up to 64 (nearest), 64 ceil(R / 64) otherwise */
+                              rounded up to 64 (nearest, Poisson), 64 ceil(R / 64)
+                              otherwise */
     int32_t reserved;      /* must be 0 */
 } pa_config;
 

@@ -20,17 +20,18 @@ LIB_PATH = os.path.join(_PKG, "libpa.so")
 
 PA_OK = 0
 PA_ERR_ARG, PA_ERR_NOMEM, PA_ERR_DEVICE, PA_ERR_CAPACITY = -1, -2, -3, -4
-PA_ERR_DONE, PA_ERR_STATE, PA_ERR_NUMERIC = -5, -6, -7
-PA_RESAMPLE_NEAREST, PA_RESAMPLE_MULTINOMIAL, PA_RESAMPLE_NONE = 0, 1, 2
+PA_ERR_DONE, PA_ERR_STATE, PA_ERR_NUMERIC, PA_ERR_EXTINCT = -5, -6, -7, -8
+PA_RESAMPLE_NEAREST, PA_RESAMPLE_MULTINOMIAL, PA_RESAMPLE_NONE, PA_RESAMPLE_POISSON = 0, 1, 2, 3
 PA_LAYOUT_INT8, PA_LAYOUT_MSC64 = 0, 1
 PA_MLP_IN, PA_MLP_HIDDEN = 35, 64
 PA_MLP_PARAMS = 64 * 35 + 64 + 64 * 64 + 64 + 64 + 1
 
 RESAMPLE = {"nearest": PA_RESAMPLE_NEAREST, "multinomial": PA_RESAMPLE_MULTINOMIAL,
-            "none": PA_RESAMPLE_NONE}
+            "none": PA_RESAMPLE_NONE, "poisson": PA_RESAMPLE_POISSON}
 LAYOUT = {"int8": PA_LAYOUT_INT8, "msc64": PA_LAYOUT_MSC64}
 _STATUS = {0: "PA_OK", -1: "PA_ERR_ARG", -2: "PA_ERR_NOMEM", -3: "PA_ERR_DEVICE",
-           -4: "PA_ERR_CAPACITY", -5: "PA_ERR_DONE", -6: "PA_ERR_STATE", -7: "PA_ERR_NUMERIC"}
+           -4: "PA_ERR_CAPACITY", -5: "PA_ERR_DONE", -6: "PA_ERR_STATE", -7: "PA_ERR_NUMERIC",
+           -8: "PA_ERR_EXTINCT"}
 
 
 class pa_config(ctypes.Structure):

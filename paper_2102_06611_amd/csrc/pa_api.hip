@@ -26,7 +26,7 @@ int default_capacity(const pa_config &c) {
     int64_t cap;
     if (c.capacity > 0)
         cap = c.capacity;
-    else if (c.resample == PA_RESAMPLE_NEAREST)
+    else if (c.resample == PA_RESAMPLE_NEAREST || c.resample == PA_RESAMPLE_POISSON)
         cap = (int64_t)c.R + (int64_t)std::ceil(10.0 * std::sqrt((double)c.R));
     else
         cap = c.R;
@@ -42,7 +42,7 @@ bool validate(const pa_config &c, std::string *why) {
     if (c.R < 1 || c.R > (1 << 24)) return fail("R must be in [1, 2^24]");
     if (c.n_steps < 0 || c.n_steps > 10000000) return fail("n_steps must be in [0, 1e7]");
     if (c.theta < 0 || c.theta > 1000000) return fail("theta must be in [0, 1e6]");
-    if (c.resample < 0 || c.resample > 2) return fail("unknown resampling rule");
+    if (c.resample < 0 || c.resample > 3) return fail("unknown resampling rule");
     if (c.layout < 0 || c.layout > 1) return fail("unknown layout");
     if (c.capacity < 0) return fail("capacity must be >= 0");
     if (c.capacity > 0 && c.capacity < c.R) return fail("capacity must be >= R");
@@ -60,7 +60,7 @@ bool validate(const pa_config &c, std::string *why) {
 struct RunPlan {
     int L, N, R, C, G, K, nblk, max_steps;
     size_t off_ms[2], off_s8[2], off_E, off_M, off_fam[2], off_hist, off_zlev, off_wlev,
-        off_cnt, off_off, off_par, off_cum, off_part, off_partd, off_blk, off_betas, off_records, off_st,
+        off_plev, off_cnt, off_off, off_par, off_cum, off_part, off_partd, off_blk, off_betas, off_records, off_st,
         off_stage, off_feat, off_flog, off_tlog, off_alog, off_alpha;
     size_t bytes;
 };
@@ -98,6 +98,7 @@ RunPlan plan_run(const pa_config &c) {
     p.off_hist = take((size_t)p.K * 4);
     p.off_zlev = take((size_t)p.K * 8);
     p.off_wlev = take((size_t)p.K * 16);
+    p.off_plev = take((size_t)p.K * 48);
     p.off_cnt = take((size_t)p.C * 4);
     p.off_off = take((size_t)(p.C + 1) * 4);
     p.off_par = take((size_t)p.C * 4);
@@ -353,6 +354,7 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         d.hist = (int32_t *)(base + p.off_hist);
         d.zlev = (uint64_t *)(base + p.off_zlev);
         d.wlev = (double *)(base + p.off_wlev);
+        d.plev = (double *)(base + p.off_plev);
         d.cnt = (int32_t *)(base + p.off_cnt);
         d.off = (int32_t *)(base + p.off_off);
         d.par = (int32_t *)(base + p.off_par);
@@ -421,10 +423,11 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         pa_status e = upload_class_map(B, (int)k);
         if (e) return e;
     }
-    lc.any_nearest = lc.any_multi = false;
+    lc.any_nearest = lc.any_multi = lc.any_poisson = false;
     lc.any_msc = lc.any_int8 = false;
     for (int r = 0; r < n; ++r) {
         if (cfgs[r].resample == PA_RESAMPLE_MULTINOMIAL) lc.any_multi = true;
+        else if (cfgs[r].resample == PA_RESAMPLE_POISSON) lc.any_poisson = true;
         else lc.any_nearest = true;
         if (cfgs[r].layout == PA_LAYOUT_MSC64) lc.any_msc = true;
         else lc.any_int8 = true;

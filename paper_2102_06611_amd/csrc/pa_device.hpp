@@ -32,6 +32,7 @@ constexpr uint32_t kTagSweep = 0x10000000u;
 constexpr uint32_t kTagInit = 0x20000000u;
 constexpr uint32_t kTagResample = 0x30000000u;
 constexpr uint32_t kTagMulti = 0x40000000u;
+constexpr uint32_t kTagPoisson = 0x50000000u;
 
 // Dynamic per-run state, written only by kernels once a run exists.
 struct RunState {
@@ -70,6 +71,7 @@ struct RunDesc {
     int32_t *hist;             // [K] energy histogram, level k <-> E = -2N + 4k
     uint64_t *zlev;            // [K] per-level decision integers (from kmin)
     double *wlev;              // [2K] per-level Boltzmann factor (double-double, from kmin)
+    double *plev;              // [6K] Poisson, per level: tau_hat, m, k with e^-tau_hat = m 2^-k
     int32_t *cnt;              // [C] copy counts of the last resampling
     int32_t *off;              // [C + 1] exclusive offsets of the children
     int32_t *par;              // [C] parent of each child slot of the last resampling
@@ -233,15 +235,11 @@ __device__ constexpr dd kRecip[14] = {
     {0x1.2492492492492p-4, 0x1.2492492492492p-58},  // 1/14
 };
 
-// exp(-x) for x >= 0 given in double-double.  Returns false (and sets *out to
-// 0) when exp(-x) < 2^-1000, i.e. far below every decision boundary here.
+// exp(-x) = m 2^-k for x >= 0 given in double-double (m in [0.7, 1.42]).
 // Range reduction x = k ln 2 + r, |r| <= ln 2 / 2; then r / 16 and a Taylor
-// series of 14 terms, squared four times.  Relative error below 2^-98.
-__device__ inline bool dd_exp_neg(dd x, dd *out) {
-    if (x.hi > 690.0) {
-        *out = dd{0.0, 0.0};
-        return false;
-    }
+// series of 14 terms, squared four times.  Relative error of m below 2^-98
+// plus k 2^-106 from the reduction.
+__device__ inline dd dd_exp_neg_split(dd x, int *kexp) {
     double k = rint(x.hi / 6.93147180559945286227e-01);
     dd r = dd_sub(x, dd_mul_d(dd_ln2(), k));  // e^-x = 2^-k e^-r
     dd rs = dd_ldexp(dd_neg(r), -4);          // -r / 16
@@ -253,7 +251,19 @@ __device__ inline bool dd_exp_neg(dd x, dd *out) {
         sum = dd_add(sum, term);
     }
     for (int s = 0; s < 4; ++s) sum = dd_mul(sum, sum);
-    *out = dd_ldexp(sum, -(int)k);
+    *kexp = (int)k;
+    return sum;
+}
+// exp(-x) for x >= 0 given in double-double.  Returns false (and sets *out to
+// 0) when exp(-x) < 2^-1000, i.e. far below every decision boundary here.
+__device__ inline bool dd_exp_neg(dd x, dd *out) {
+    if (x.hi > 690.0) {
+        *out = dd{0.0, 0.0};
+        return false;
+    }
+    int k;
+    const dd m = dd_exp_neg_split(x, &k);
+    *out = dd_ldexp(m, -k);
     return true;
 }
 

@@ -30,7 +30,7 @@ struct LaunchCtx {
     MapInfo slots;   // per run: nblk blocks of kSlotBlock slots
     MapInfo groups;  // per run: G blocks, one per 64-replica group
     std::vector<SweepClass> sweep_classes;  // one launch per distinct L
-    bool any_nearest, any_multi;
+    bool any_nearest, any_multi, any_poisson;
     bool any_msc, any_int8;  // layouts present in the batch
 };
 

@@ -171,12 +171,19 @@ __global__ void __launch_bounds__(256) k_hist(const RunDesc *runs, WorkMap map) 
 //   S = sum_l n_l w_l,   ln Q_i = -dB E_min + ln(S / R_{i-1})          (Eq. Q)
 //   nearest:     Z_l = ceil(2^32 R w_l / S) = ceil(2^32 tau_hat)      (Eq. taus)
 //   multinomial: q_l = floor(2^40 w_l)
+//   Poisson:     lambda_l = R w_l / S = tau_hat and e^{-lambda_l} = m 2^-e,
+//                double-double (plev[6l .. 6l+4]); an occupied level with
+//                lambda_l > kPoissonMaxMean fails with PA_ERR_NUMERIC
 // Z_l and q_l are the exact integers of the real-valued definitions: they are
 // computed in double-double and a value within the error margin of an integer
 // boundary aborts the run with PA_ERR_NUMERIC.  dB = 0 or a single occupied
 // level make every w_l = 1 and S = R_{i-1} exactly; those use integer math.
 // Also: the Metropolis thresholds t4 = ceil(2^32 e^{-4 beta_i}), t8 =
 // ceil(2^32 e^{-8 beta_i}) and the end-of-schedule check.
+constexpr double kPoissonMaxMean = 65536.0;  // largest supported tau_hat
+constexpr int kPoissonMax = 1 << 18;          // > kPoissonMaxMean + 40 sqrt(kPoissonMaxMean)
+constexpr double kPoissonMargin = 0x1p-8;     // in units of U
+
 __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     const RunDesc &rd = runs[blockIdx.x];
     RunState *st = rd.st;
@@ -270,8 +277,24 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     bool amb = false;
     const double R2_32 = ldexp((double)rd.R, 32);
     for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
-        uint64_t z;
-        if (rd.resample == PA_RESAMPLE_MULTINOMIAL) {
+        uint64_t z = 0;
+        if (rd.resample == PA_RESAMPLE_POISSON) {
+            const dd w{rd.wlev[2 * l], rd.wlev[2 * l + 1]};
+            dd lam{0.0, 0.0}, m{1.0, 0.0};  // w_l = 0: tau_hat < 2^-900, no copies
+            int e = 0;
+            if (exact)
+                lam = dd_div_d(dd{(double)rd.R, 0.0}, (double)Rp);
+            else if (w.hi != 0.0)
+                lam = dd_div(dd_mul_d(w, (double)rd.R), S);
+            if (lam.hi != 0.0) m = dd_exp_neg_split(lam, &e);
+            if (!(lam.hi <= kPoissonMaxMean) && rd.hist[kmin + l] != 0) amb = true;
+            double *p = rd.plev + 6 * l;
+            p[0] = lam.hi;
+            p[1] = lam.lo;
+            p[2] = m.hi;
+            p[3] = m.lo;
+            p[4] = (double)e;
+        } else if (rd.resample == PA_RESAMPLE_MULTINOMIAL) {
             if (exact || l == 0) {
                 z = 1ull << 40;
             } else {
@@ -315,7 +338,8 @@ __global__ void __launch_bounds__(256) k_counts_nearest(const RunDesc *runs, Wor
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
-    if (st->err || rd.resample == PA_RESAMPLE_MULTINOMIAL) return;
+    if (st->err || rd.resample == PA_RESAMPLE_MULTINOMIAL || rd.resample == PA_RESAMPLE_POISSON)
+        return;
     __shared__ int64_t sh[32];
     const int Rp = st->R_cur, i = st->step + 1, kmin = st->kmin;
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
@@ -346,6 +370,83 @@ __global__ void __launch_bounds__(256) k_counts_nearest(const RunDesc *runs, Wor
     if (threadIdx.x == 0) {
         rd.part[b * 8 + 0] = v[0];
         rd.part[b * 8 + 1] = v[1];
+    }
+}
+
+// Poisson rule (Sec. "Algorithm", fluctuating population): r_j is the
+// smallest k with U_j < 2^64 F(k), F the CDF of Poisson(lambda) with lambda =
+// tau_hat of the parent's level and U_j its 64-bit uniform (POISSON stream:
+// counter j/2, words 0-1 for even j, 2-3 for odd j, low word first).  F(k) =
+// e^-lambda sum_{m<=k} lambda^m / m! in double-double: relative error below
+// 2^-80 for lambda <= kPoissonMaxMean (from lambda's own error, ~lambda 2^-98,
+// and k 2^-104 over the recursion), i.e. below 2^-16 in units of U; a
+// comparison closer than kPoissonMargin, or no decision by kPoissonMax, fails
+// with PA_ERR_NUMERIC.
+// F(k) = G 2^-e: G starts as the mantissa of e^-lambda and is scaled down by
+// 2^512 whenever it passes 2^512, so that neither a tiny e^-lambda nor the
+// growing terms leave the binary64 range.
+__device__ inline int poisson_invert(dd lam, dd G, int e, uint64_t U, bool *amb) {
+    const dd Ud = dd_add(dd{(double)(U >> 32) * 4294967296.0, 0.0}, dd{(double)(uint32_t)U, 0.0});
+    dd term = G;
+    for (int k = 0; k < kPoissonMax; ++k) {
+        const dd gap = dd_sub(dd_ldexp(G, 64 - e), Ud);
+        if (gap.hi > kPoissonMargin) return k;  // U < 2^64 F(k)
+        if (gap.hi > -kPoissonMargin) {
+            *amb = true;
+            return k;
+        }
+        term = dd_div_d(dd_mul(term, lam), (double)(k + 1));
+        G = dd_add(G, term);
+        if (G.hi > 0x1p512) {
+            G = dd_ldexp(G, -512);
+            term = dd_ldexp(term, -512);
+            e -= 512;
+        }
+    }
+    *amb = true;
+    return kPoissonMax;
+}
+
+__global__ void __launch_bounds__(256) k_counts_poisson(const RunDesc *runs, WorkMap map) {
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    if (st->err || rd.resample != PA_RESAMPLE_POISSON) return;
+    __shared__ int64_t sh[32];
+    __shared__ int amb_any;
+    if (threadIdx.x == 0) amb_any = 0;
+    const int Rp = st->R_cur, i = st->step + 1, kmin = st->kmin;
+    const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
+    int64_t s = 0, s2 = 0;
+    bool amb = false;
+    if (j < Rp) {
+        const U4 x0 = philox(rd.key0, rd.key1, (uint32_t)(j >> 1), (uint32_t)i, 0u, kTagPoisson);
+        const U4 x1 = philox(rd.key0, rd.key1, (uint32_t)(j >> 1) + 1u, (uint32_t)i, 0u, kTagPoisson);
+        const uint64_t U[4] = {((uint64_t)x0.y << 32) | x0.x, ((uint64_t)x0.w << 32) | x0.z,
+                               ((uint64_t)x1.y << 32) | x1.x, ((uint64_t)x1.w << 32) | x1.z};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int jj = j + m;
+            if (jj < Rp) {
+                const double *p = rd.plev + 6 * (((rd.E[jj] + 2 * rd.N) >> 2) - kmin);
+                const int c = poisson_invert(dd{p[0], p[1]}, dd{p[2], p[3]}, (int)p[4], U[m], &amb);
+                rd.cnt[jj] = c;
+                s += c;
+                s2 += (int64_t)c * c;
+            }
+        }
+    }
+    __syncthreads();
+    if (amb) atomicOr(&amb_any, 1);
+    int64_t v[2] = {s, s2};
+    block_sum_i64v(v, sh);  // its barriers also order amb_any
+    if (threadIdx.x == 0) {
+        rd.part[b * 8 + 0] = v[0];
+        rd.part[b * 8 + 1] = v[1];
+        if (amb_any) {
+            st->err = PA_ERR_NUMERIC;
+            st->err_step = i;
+        }
     }
 }
 
@@ -484,7 +585,8 @@ __global__ void __launch_bounds__(256) k_count_partials(const RunDesc *runs, Wor
 }
 
 // off[j] = sum_{l<j} r_l (children of parent j occupy [off[j], off[j] + r_j)),
-// off[R_{i-1}] = R_i, and par[c] = j for those children.  Block 0 records R_i (or PA_ERR_CAPACITY) and
+// off[R_{i-1}] = R_i, and par[c] = j for those children.  Block 0 records R_i (or PA_ERR_CAPACITY,
+// PA_ERR_EXTINCT) and
 // sum r_j^2.  The histogram, consumed by k_norm, is cleared here so that the
 // reduction at the end of the step can build the next one.
 __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap map) {
@@ -513,8 +615,8 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
     if (b == 0) {
         const int64_t total = v[1], sq = v[2];
         if (threadIdx.x == 0) {
-            if (total > rd.C) {
-                st->err = PA_ERR_CAPACITY;
+            if (total > rd.C || total == 0) {
+                st->err = total ? PA_ERR_CAPACITY : PA_ERR_EXTINCT;
                 st->err_step = st->step + 1;
             } else {
                 st->R_new = (int32_t)total;
@@ -1930,6 +2032,8 @@ hipError_t launch_counts(const LaunchCtx &c) {
     if (c.any_nearest)
         PA_LAUNCH(k_counts_nearest, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
+    if (c.any_poisson)
+        PA_LAUNCH(k_counts_poisson, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
     if (c.any_multi) {
         PA_LAUNCH(k_multi_weights, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);

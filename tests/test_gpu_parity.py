@@ -111,6 +111,11 @@ CASES = [
     # boundaries (the first grows one family over five blocks)
     (6, 5000, 0, 6, 2.0, "nearest", "msc64"),
     (4, 5000, 1, 6, 3.0, "multinomial", "int8"),
+    # Poisson resampling: fluctuating R_i, several blocks, strong selection
+    (8, 200, 3, 8, 0.44, "poisson", "msc64"),
+    (6, 130, 2, 6, 0.6, "poisson", "int8"),
+    (4, 64, 5, 10, 1.2, "poisson", "msc64"),
+    (6, 5000, 0, 6, 2.0, "poisson", "msc64"),
 ]
 
 
@@ -248,6 +253,34 @@ def test_capacity_overflow_is_reported_and_state_kept():
     assert len(ref.E) > 128  # the step that overflowed
 
 
+def test_extinct_population_is_reported():
+    # R = 2, Poisson: for some seeds both parents draw zero copies at step 1
+    # (seeds 27 and 35 among 20..39); the device reports PA_ERR_EXTINCT
+    # exactly where the oracle stops
+    L, R, betas = 4, 2, [0.0, 0.3, 0.6]
+    extinct = 0
+    for seed in range(20, 40):
+        ref = po.OracleRun(L, R, 1, seed, "poisson", betas)
+        run = pa.Run(L, R, betas, 1, seed, "poisson", "msc64")
+        try:
+            ref.anneal_step()
+            ok = True
+        except po.PopulationExtinct:
+            ok = False
+        run.anneal_step()
+        if ok:
+            run.sync()
+            check_record(run.observables(1), ref.records[1], "seed %d" % seed)
+        else:
+            with pytest.raises(pa.PAError) as ei:
+                run.sync()
+            assert ei.value.status == pa.PA_ERR_EXTINCT, seed
+            assert run.current() == (0, R)  # the population before the step is kept
+            extinct += 1
+        run.close()
+    assert extinct > 0
+
+
 def test_schedule_end_is_reported():
     run = pa.Run(8, 64, linear_schedule(0.3, 2), 1, 1, "nearest", "msc64")
     run.anneal_step()
@@ -304,6 +337,13 @@ def test_l64_multinomial_sampled_step_parity(layout):
     """L=64, R=100000, multinomial, beta 0 -> 0.4407 in 200 steps: step 120 -> 121."""
     log("L64 sampled", layout)
     _sampled_step_parity(64, 100_000, "multinomial", layout, 200, 0.4407, 120, 10, PARITY_SEED)
+
+
+@pytest.mark.slow
+def test_l64_poisson_sampled_step_parity():
+    """L=64, R=100000, Poisson, beta 0 -> 0.4407 in 200 steps: step 120 -> 121."""
+    log("L64 sampled poisson")
+    _sampled_step_parity(64, 100_000, "poisson", "msc64", 200, 0.4407, 120, 10, PARITY_SEED)
 
 
 @pytest.mark.slow
