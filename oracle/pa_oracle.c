@@ -129,6 +129,30 @@ void oracle_word_uniforms(uint64_t seed, uint32_t w, uint32_t g, uint32_t h, con
     }
 }
 
+/*
+ * Heatbath uniforms of word (w, g, h): as oracle_word_uniforms, except that a
+ * lane counts as tied only when the top six bits leave u < thr[l] undecided,
+ * i.e. they equal those of thr[l] and the low 26 bits of thr[l] are not all
+ * zero (with a zero low part, equal top bits already give u >= thr[l]).
+ */
+void oracle_word_uniforms_heatbath(uint64_t seed, uint32_t w, uint32_t g, uint32_t h,
+                                   const uint64_t thr[64], const int needs[64], uint32_t u[64]) {
+    uint32_t ties = 0;
+    for (uint32_t l = 0; l < 64; ++l) {
+        u[l] = 0;
+        if (!needs[l])
+            continue;
+        uint32_t top = oracle_sweep_top6(seed, w, g, h, l);
+        u[l] = top << 26;
+        if (top == (uint32_t)(thr[l] >> 26) && (thr[l] & 0x3FFFFFFu) != 0) {
+            uint32_t x[4];
+            draw(seed, w, g, h, TAG_TIE | (ties >> 2), x);
+            u[l] |= x[ties & 3u] >> 6;
+            ++ties;
+        }
+    }
+}
+
 uint32_t oracle_resample_uniform(uint64_t seed, uint32_t step, uint32_t j) {
     uint32_t x[4];
     draw(seed, j >> 2, step, 0, TAG_RESAMPLE, x);
@@ -252,6 +276,61 @@ void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int the
                             else
                                 flip = (uint64_t)u[l] < thr[l];
                             if (flip)
+                                s[site] = (int8_t)(-s[site]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+/*
+ * theta checkerboard heatbath sweeps (Sec. "Spin updates": heatbath, the same
+ * as Glauber dynamics for Ising spins) at beta_i of step i >= 1, in the order
+ * of oracle_sweeps.  The spin at a site flips with probability
+ * 1 / (1 + exp(beta dE)), dE the energy change of the flip, whatever its sign;
+ * equivalently the new spin is +1 with probability 1 / (1 + exp(-2 beta h)),
+ * h the sum of the four neighbours.  thr[c] = ceil(2^32 / (1 + exp(beta dE)))
+ * for dE = 4c - 8 (c = 0..4) is passed in; the flip happens iff u < thr[c],
+ * u the lane's uniform (oracle_word_uniforms_heatbath).  Every replica
+ * compares, so every valid lane draws.
+ */
+void oracle_sweeps_heatbath(uint64_t seed, int L, int R, int8_t *spins, int step, int theta,
+                            const uint64_t thr5[5], int slot0) {
+    int N = L * L;
+    int half = L / 2;
+    for (int sweep = 0; sweep < theta; ++sweep) {
+        for (int colour = 0; colour < 2; ++colour) {
+            uint32_t h = (uint32_t)(2 * (theta * (step - 1) + sweep) + colour);
+            for (int r0 = 0; r0 < R; r0 += 64) {
+                int n_lanes = R - r0 < 64 ? R - r0 : 64;
+                uint32_t g = (uint32_t)((slot0 + r0) / 64);
+                for (int y = 0; y < L; ++y) {
+                    for (int x = 0; x < L; ++x) {
+                        if (((x + y) & 1) != colour)
+                            continue;
+                        int site = y * L + x;
+                        uint64_t thr[64];
+                        int needs[64];
+                        uint32_t u[64];
+                        for (int l = 0; l < 64; ++l) {
+                            thr[l] = 0;
+                            needs[l] = 0;
+                            if (l >= n_lanes)
+                                continue;
+                            const int8_t *s = spins + (size_t)(r0 + l) * N;
+                            int field = s[y * L + (x + 1) % L] + s[y * L + (x + L - 1) % L] +
+                                        s[((y + 1) % L) * L + x] + s[((y + L - 1) % L) * L + x];
+                            int dE = oracle_delta_energy(s[site], field);
+                            thr[l] = thr5[(dE + 8) / 4];
+                            needs[l] = 1;
+                        }
+                        oracle_word_uniforms_heatbath(seed, (uint32_t)(y * half + x / 2), g, h, thr,
+                                                      needs, u);
+                        for (int l = 0; l < n_lanes; ++l) {
+                            int8_t *s = spins + (size_t)(r0 + l) * N;
+                            if ((uint64_t)u[l] < thr[l])
                                 s[site] = (int8_t)(-s[site]);
                         }
                     }

@@ -28,7 +28,9 @@ file takes the per-step decisions, following Sec. "Algorithm" steps 1-5:
   weight exceeds floor(U * W / 2^64), W the total.
 * Copies of one parent sit at adjacent slots, parents in ascending order
   (Sec. "Overlap correlation": place the r copies at adjacent indices).
-* Metropolis thresholds ceil(2^32 exp(-beta dE)) for dE = 4, 8.
+* Metropolis thresholds ceil(2^32 exp(-beta dE)) for dE = 4, 8; heatbath
+  (Sec. "Spin updates") thresholds ceil(2^32 / (1 + exp(beta dE))) for
+  dE = -8, -4, 0, 4, 8 (every move compares).
 * Eq. (free-emergy-estimator): -beta_i F_i = ln Z_0 + sum_k ln Q_k with
   ln Z_0 = L^2 ln 2.
 * Sec. "Model and observables": e, C_V, m, chi from population sums (N -> R_i).
@@ -111,6 +113,11 @@ def lib():
         L.oracle_delta_energy.restype = i32
         L.oracle_sweeps.argtypes = [u64, i32, i32, p_i8, i32, i32, u64, u64, i32]
         L.oracle_sweeps.restype = None
+        L.oracle_word_uniforms_heatbath.argtypes = L.oracle_word_uniforms.argtypes
+        L.oracle_word_uniforms_heatbath.restype = None
+        L.oracle_sweeps_heatbath.argtypes = [u64, i32, i32, p_i8, i32, i32,
+                                             ctypes.POINTER(ctypes.c_uint64), i32]
+        L.oracle_sweeps_heatbath.restype = None
         _lib = L
     return _lib
 
@@ -144,6 +151,18 @@ def word_uniforms(seed: int, w: int, g: int, h: int, thr, needs) -> np.ndarray:
     u = np.zeros(64, dtype=np.uint32)
     lib().oracle_word_uniforms(seed, w, g, h, _ptr(t, ctypes.c_uint64), _ptr(n, ctypes.c_int),
                                _ptr(u, ctypes.c_uint32))
+    return u
+
+
+def word_uniforms_heatbath(seed: int, w: int, g: int, h: int, thr, needs) -> np.ndarray:
+    """The 64 heatbath uniforms of word (w, g, h): as word_uniforms, but a lane
+    is tied only when its top six bits leave u < thr undecided."""
+    t = np.ascontiguousarray(np.asarray(thr, dtype=np.uint64))
+    n = np.ascontiguousarray(np.asarray(needs, dtype=np.intc))
+    assert t.shape == (64,) and n.shape == (64,)
+    u = np.zeros(64, dtype=np.uint32)
+    lib().oracle_word_uniforms_heatbath(seed, w, g, h, _ptr(t, ctypes.c_uint64),
+                                        _ptr(n, ctypes.c_int), _ptr(u, ctypes.c_uint32))
     return u
 
 
@@ -213,6 +232,20 @@ def sweeps(seed: int, L: int, spins: np.ndarray, step: int, theta: int, t4: int,
         lib().oracle_sweeps(seed, L, R, _ptr(spins, ctypes.c_int8), step, theta, t4, t8, slot0)
 
 
+def sweeps_heatbath(seed: int, L: int, spins: np.ndarray, step: int, theta: int, thr5,
+                    slot0: int = 0) -> None:
+    """theta checkerboard heatbath sweeps, in place, for step >= 1; thr5[c] is
+    heatbath_threshold(beta, 4c - 8).  Groups as in sweeps()."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous
+    assert slot0 % 64 == 0, "sweeps take whole 64-replica groups"
+    t = np.ascontiguousarray(np.asarray(thr5, dtype=np.uint64))
+    assert t.shape == (5,)
+    R = spins.shape[0]
+    if R and theta:
+        lib().oracle_sweeps_heatbath(seed, L, R, _ptr(spins, ctypes.c_int8), step, theta,
+                                     _ptr(t, ctypes.c_uint64), slot0)
+
+
 # ---------------------------------------------------------------- decisions
 
 def _check_margin(x, what: str):
@@ -230,6 +263,24 @@ def metropolis_threshold(beta: float, dE: int) -> int:
     with mpmath.workprec(PREC_BITS):
         x = mpmath.ldexp(mpmath.exp(-mpmath.mpf(beta) * dE), 32)
         _check_margin(x, "2^32 exp(-beta dE)")
+        return int(mpmath.ceil(x))
+
+
+def heatbath_threshold(beta: float, dE: int) -> int:
+    """ceil(2^32 / (1 + exp(beta dE))): the heatbath flip (Sec. "Spin updates")
+    of a move with energy change dE happens iff u32 < this value.  beta = 0 or
+    dE = 0 give probability 1/2, i.e. 2^31 exactly."""
+    if beta == 0.0 or dE == 0:
+        return 1 << 31
+    # for dE < 0, 2^32 p lies about 2^32 exp(-beta |dE|) below 2^32: carry
+    # enough extra bits that the rounding error stays far below that distance
+    prec = PREC_BITS + int(abs(beta * dE) * 1.5) + 64
+    with mpmath.workprec(prec):
+        x = mpmath.ldexp(1 / (1 + mpmath.exp(mpmath.mpf(beta) * dE)), 32)
+        gap = min(x - mpmath.floor(x), mpmath.ceil(x) - x)
+        if gap < mpmath.mpf(2) ** (32 + 100 - prec):
+            raise OracleAmbiguity("2^32 / (1 + exp(beta dE)) = %s is too close to an integer"
+                                  % mpmath.nstr(x, 40))
         return int(mpmath.ceil(x))
 
 
@@ -316,11 +367,13 @@ class OracleRun:
     """
 
     def __init__(self, L: int, R: int, theta: int, seed: int, resample: str = "nearest",
-                 betas: Optional[np.ndarray] = None):
+                 betas: Optional[np.ndarray] = None, update: str = "metropolis"):
         assert L >= 4 and L % 2 == 0
         assert resample in ("nearest", "multinomial", "poisson", "none")
+        assert update in ("metropolis", "heatbath")
         self.L, self.N, self.R, self.theta, self.seed = L, L * L, R, theta, seed
         self.resample = resample
+        self.update = update
         self.betas: List[float] = [0.0] if betas is None else [float(b) for b in betas]
         assert self.betas[0] == 0.0
         self.step = 0
@@ -417,9 +470,13 @@ class OracleRun:
         with mpmath.workprec(PREC_BITS):
             self._acc = self._acc + ln_q
         self.step = i
-        t4 = metropolis_threshold(beta, 4)
-        t8 = metropolis_threshold(beta, 8)
-        sweeps(self.seed, self.L, self.spins, i, self.theta, t4, t8)
+        if self.update == "heatbath":
+            thr5 = [heatbath_threshold(beta, dE) for dE in (-8, -4, 0, 4, 8)]
+            sweeps_heatbath(self.seed, self.L, self.spins, i, self.theta, thr5)
+        else:
+            t4 = metropolis_threshold(beta, 4)
+            t8 = metropolis_threshold(beta, 8)
+            sweeps(self.seed, self.L, self.spins, i, self.theta, t4, t8)
         self.E, self.M = energy_magnetisation(self.L, self.spins)
         rec = self._record(ln_q, int((counts.astype(np.int64) ** 2).sum()))
         self.records.append(rec)
@@ -442,9 +499,10 @@ class OracleRun:
             self.betas = [float(b) for b in betas]
 
 
-def run(L: int, R: int, betas, theta: int, seed: int, resample: str = "nearest") -> OracleRun:
+def run(L: int, R: int, betas, theta: int, seed: int, resample: str = "nearest",
+        update: str = "metropolis") -> OracleRun:
     """A whole run over the schedule betas[0] = 0 < betas[1] < ... ."""
-    o = OracleRun(L, R, theta, seed, resample, np.asarray(betas, dtype=np.float64))
+    o = OracleRun(L, R, theta, seed, resample, np.asarray(betas, dtype=np.float64), update)
     for _ in range(len(betas) - 1):
         o.anneal_step()
     return o
