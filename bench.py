@@ -52,18 +52,19 @@ def measured_traffic(kernel: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial", seed=SEED):
+def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial", seed=SEED,
+                update="metropolis"):
     from paper_2102_06611_amd import autotune
     stream = torch.cuda.Stream()
     # warmup: W steps of a separate run (brings clocks and caches up)
     if W > 0:
-        w = pa.Run(L, R, betas, THETA, seed + 1, resample, layout, stream=stream)
+        w = pa.Run(L, R, betas, THETA, seed + 1, resample, layout, stream=stream, update=update)
         autotune.apply(w, L, R, layout)
         for _ in range(min(W, len(betas) - 1)):
             w.anneal_step()
         w.sync()
         w.close()
-    run = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream)
+    run = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream, update=update)
     geometry = autotune.apply(run, L, R, layout) or run.sweep_launch(L)
     run.sync()
     torch.cuda.synchronize()
@@ -80,7 +81,7 @@ def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial"
     # same populations, same calls)
     prof = None
     for count in (False, True):
-        prun = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream)
+        prun = pa.Run(L, R, betas, THETA, seed, resample, layout, stream=stream, update=update)
         autotune.apply(prun, L, R, layout)
         prun.profile(True, count_calls=count)
         for _ in range(K):
@@ -188,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layouts", default="msc64,int8")
     ap.add_argument("--headline-only", action="store_true")
+    ap.add_argument("--update", choices=("metropolis", "heatbath"), default="metropolis",
+                    help="spin update of the layout runs (profiling the heatbath sweep)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -215,7 +218,8 @@ def main():
     energies_mid = None
     for layout in args.layouts.split(","):
         log("timing layout %s: %d steps" % (layout, K))
-        run, wall, prof, recs, attempts = time_layout(pa, torch, betas, layout, K, args.warmup)
+        run, wall, prof, recs, attempts = time_layout(pa, torch, betas, layout, K, args.warmup,
+                                                      update=args.update)
         n = prof["steps"]
         sweep_ms = prof["ms_sweep"] / n
         res_ms = prof["ms_resample"] / n
@@ -287,6 +291,22 @@ def main():
                 "beta_f_error_per_spin_at_last_step": err}
             run.close()
             torch.cuda.empty_cache()
+        log("timing L=64, R=100000, multinomial, heatbath, multispin: %d steps" % K)
+        run, wall, prof, recs, attempts = time_layout(pa, torch, betas, "msc64", K, 0,
+                                                      update="heatbath")
+        n = prof["steps"]
+        words, calls = prof["sweep_words"] / n, prof["philox_calls"] / n
+        sweep_ms = prof["ms_sweep"] / n
+        alg = calls * (SLOTS_PER_PHILOX + SLOTS_PER_PLANE_PAIR) + words * SLOTS_PER_WORD
+        extra["l64_heatbath_msc64"] = {
+            "attempts_per_ns": attempts / wall / 1e9, "ms_per_step": wall * 1e3 / K,
+            "sweep_attempts_per_ns": attempts / (prof["ms_sweep"] * 1e-3) / 1e9,
+            "sweep_ms_per_step": sweep_ms, "philox_calls_per_word": calls / words if words else 0.0,
+            "sweep_alu_tops": alg / (sweep_ms * 1e-3) / 1e12,
+            "sweep_alu_frac": alg / (sweep_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+            "beta_f_error_per_spin_at_last_step": abs(recs[-1]["minus_beta_F"] - lnz[K]) / (L * L)}
+        run.close()
+        torch.cuda.empty_cache()
         log("timing the 64-run batch: 200 steps")
         extra["batched_64_runs"] = time_batch(pa, torch, 200)
         torch.cuda.empty_cache()
@@ -308,7 +328,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64 bit-sliced (int32 counts, f64 ln Q)",
         "data": "synthetic",
         "config": {"workload": "2D Ising L=64 periodic, R=100000, multinomial resampling, beta 0->0.4407 "
-                               "in 200 steps, theta=10, %s layout" % head_layout,
+                               "in 200 steps, theta=10, %s layout, %s update" % (head_layout, args.update),
                    "L": L, "R": R, "theta": THETA, "n_steps": N_STEPS, "seed": SEED,
                    "steps_timed": "1..%d" % K},
         "resample_us_per_step": head["resample_us_per_step"],

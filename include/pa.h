@@ -68,6 +68,12 @@ enum {
                                     Poisson CDF; fluctuating R_i */
 };
 
+/* Single-spin update of the theta sweeps (Sec. "Spin updates"). */
+enum {
+    PA_UPDATE_METROPOLIS = 0,    /* flip with probability min(1, e^{-beta dE}) */
+    PA_UPDATE_HEATBATH = 1       /* flip with probability 1 / (1 + e^{beta dE}) (Glauber) */
+};
+
 /* Device layout of the population (replica r is lane r % 64 of group r / 64). */
 enum {
     PA_LAYOUT_INT8 = 0, /* int8 spins, +1 / -1, [group][site][64 lanes] */
@@ -88,7 +94,8 @@ typedef struct pa_config {
     int32_t capacity;      /* replica slots; 0 = default: R + ceil(10 sqrt R)
                               rounded up to 64 (nearest, Poisson), 64 ceil(R / 64)
                               otherwise */
-    int32_t reserved;      /* must be 0 */
+    int32_t update;        /* PA_UPDATE_*; 0 (Metropolis) in configurations written
+                              before the field existed */
 } pa_config;
 
 /* Per-temperature record, Sec. "Model and observables" (with N -> R_i as the

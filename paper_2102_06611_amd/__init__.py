@@ -22,6 +22,8 @@ PA_OK = 0
 PA_ERR_ARG, PA_ERR_NOMEM, PA_ERR_DEVICE, PA_ERR_CAPACITY = -1, -2, -3, -4
 PA_ERR_DONE, PA_ERR_STATE, PA_ERR_NUMERIC, PA_ERR_EXTINCT = -5, -6, -7, -8
 PA_RESAMPLE_NEAREST, PA_RESAMPLE_MULTINOMIAL, PA_RESAMPLE_NONE, PA_RESAMPLE_POISSON = 0, 1, 2, 3
+PA_UPDATE_METROPOLIS, PA_UPDATE_HEATBATH = 0, 1
+UPDATE = {"metropolis": PA_UPDATE_METROPOLIS, "heatbath": PA_UPDATE_HEATBATH}
 PA_LAYOUT_INT8, PA_LAYOUT_MSC64 = 0, 1
 PA_MLP_IN, PA_MLP_HIDDEN = 35, 64
 PA_MLP_PARAMS = 64 * 35 + 64 + 64 * 64 + 64 + 64 + 1
@@ -39,7 +41,7 @@ class pa_config(ctypes.Structure):
                 ("betas", ctypes.POINTER(ctypes.c_double)), ("n_steps", ctypes.c_int32),
                 ("theta", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("resample", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("capacity", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("capacity", ctypes.c_int32), ("update", ctypes.c_int32)]
 
 
 class pa_obs(ctypes.Structure):
@@ -142,7 +144,7 @@ def _check(status: int, handle=None, batch: bool = False):
 
 def make_config(L: int, R: int, betas: Optional[Sequence[float]], theta: int, seed: int,
                 resample: str = "nearest", layout: str = "msc64", capacity: int = 0,
-                n_steps: Optional[int] = None):
+                n_steps: Optional[int] = None, update: str = "metropolis"):
     """A pa_config plus the double array it points to (keep both alive)."""
     arr = None
     if betas is not None:
@@ -151,7 +153,7 @@ def make_config(L: int, R: int, betas: Optional[Sequence[float]], theta: int, se
     else:
         n = int(n_steps)
     cfg = pa_config(L, R, arr.ctypes.data_as(_P(ctypes.c_double)) if arr is not None else None,
-                    n, theta, seed, RESAMPLE[resample], LAYOUT[layout], capacity, 0)
+                    n, theta, seed, RESAMPLE[resample], LAYOUT[layout], capacity, UPDATE[update])
     return cfg, arr
 
 
@@ -164,11 +166,12 @@ class Run:
 
     def __init__(self, L: int, R: int, betas: Optional[Sequence[float]], theta: int, seed: int,
                  resample: str = "nearest", layout: str = "msc64", capacity: int = 0,
-                 n_steps: Optional[int] = None, device: str = "cuda:0", stream=None):
+                 n_steps: Optional[int] = None, device: str = "cuda:0", stream=None,
+                 update: str = "metropolis"):
         import torch
         self.L, self.N, self.R = L, L * L, R
         self.cfg, self._betas = make_config(L, R, betas, theta, seed, resample, layout,
-                                            capacity, n_steps)
+                                            capacity, n_steps, update)
         self.max_steps = self.cfg.n_steps
         nbytes = ctypes.c_size_t()
         _check(lib().pa_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
@@ -341,7 +344,7 @@ class Batch:
         for k, s in enumerate(specs):
             cfg, arr = make_config(s["L"], s["R"], s["betas"], s["theta"], s["seed"],
                                    s.get("resample", "nearest"), s.get("layout", "msc64"),
-                                   s.get("capacity", 0))
+                                   s.get("capacity", 0), None, s.get("update", "metropolis"))
             cfgs[k] = cfg
             self._keep.append(arr)
         self.n = len(specs)

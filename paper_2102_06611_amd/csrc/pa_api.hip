@@ -46,7 +46,8 @@ bool validate(const pa_config &c, std::string *why) {
     if (c.layout < 0 || c.layout > 1) return fail("unknown layout");
     if (c.capacity < 0) return fail("capacity must be >= 0");
     if (c.capacity > 0 && c.capacity < c.R) return fail("capacity must be >= R");
-    if (c.reserved != 0) return fail("reserved must be 0");
+    if (c.update != PA_UPDATE_METROPOLIS && c.update != PA_UPDATE_HEATBATH)
+        return fail("unknown spin update");
     if (c.betas) {
         if (c.betas[0] != 0.0) return fail("betas[0] must be 0 (simple sampling start)");
         for (int i = 1; i <= c.n_steps; ++i) {
@@ -339,6 +340,7 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         d.K = p.K;
         d.theta = c.theta;
         d.resample = c.resample;
+        d.update = c.update;
         d.layout = c.layout;
         d.max_steps = p.max_steps;
         d.key0 = (uint32_t)c.seed;
@@ -425,10 +427,12 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
     }
     lc.any_nearest = lc.any_multi = lc.any_poisson = false;
     lc.any_msc = lc.any_int8 = false;
+    lc.any_update[0] = lc.any_update[1] = false;
     for (int r = 0; r < n; ++r) {
         if (cfgs[r].resample == PA_RESAMPLE_MULTINOMIAL) lc.any_multi = true;
         else if (cfgs[r].resample == PA_RESAMPLE_POISSON) lc.any_poisson = true;
         else lc.any_nearest = true;
+        lc.any_update[cfgs[r].update] = true;
         if (cfgs[r].layout == PA_LAYOUT_MSC64) lc.any_msc = true;
         else lc.any_int8 = true;
     }
@@ -705,7 +709,7 @@ namespace {
 // runs in the same state give identical snapshots.
 struct StateHeader {
     char magic[8];
-    int32_t L, R, C, layout, resample, max_steps, theta, step, R_i, pad;
+    int32_t L, R, C, layout, resample, max_steps, theta, step, R_i, update;
     uint64_t seed;
 };
 
@@ -738,6 +742,7 @@ pa_status pa_get_state(pa_ctx *ctx, void *buf, size_t cap, size_t *used) {
     std::memcpy(h.magic, "PASTATE2", 8);
     h.L = d.L; h.R = d.R; h.C = d.C; h.layout = d.layout; h.resample = d.resample;
     h.max_steps = d.max_steps; h.theta = d.theta; h.step = s.step; h.R_i = s.R_cur;
+    h.update = d.update;
     h.seed = B->cfg[0].seed;
     std::memcpy(p, &h, sizeof h); p += sizeof h;
     std::memcpy(p, &s, sizeof s); p += sizeof s;
@@ -765,7 +770,7 @@ pa_status pa_set_state(pa_ctx *ctx, const void *buf, size_t len) {
     std::memcpy(&h, p, sizeof h); p += sizeof h;
     if (std::memcmp(h.magic, "PASTATE2", 8) || h.L != d.L || h.R != d.R || h.C != d.C ||
         h.layout != d.layout || h.resample != d.resample || h.max_steps != d.max_steps ||
-        h.theta != d.theta || h.seed != B->cfg[0].seed)
+        h.theta != d.theta || h.update != d.update || h.seed != B->cfg[0].seed)
         return fail(B, PA_ERR_STATE, "snapshot belongs to another configuration");
     if (h.step < 0 || h.step > d.max_steps || h.R_i < 1 || h.R_i > d.C)
         return fail(B, PA_ERR_STATE, "snapshot state is inconsistent");

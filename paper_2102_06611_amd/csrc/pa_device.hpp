@@ -45,7 +45,7 @@ struct RunState {
     int32_t kmin, kmax;          // occupied energy levels of the current population
     double acc_hi, acc_lo;       // running -beta F (double-double)
     double lnq_hi, lnq_lo;       // ln Q of the step in progress (committed by k_reduce)
-    uint64_t t4, t8;             // Metropolis thresholds at beta_i (2^32 = always)
+    uint64_t t4, t8;             // thresholds at beta_i (2^32: beta_i = 0), by update rule
     uint64_t w_total;            // multinomial: total quantised weight
     int64_t sum_cnt2;            // sum of squared copy counts of the step
     double dbeta_out, alpha_out; // results of the overlap / adaptive kernels
@@ -61,6 +61,7 @@ struct RunState {
 struct RunDesc {
     int32_t L, N, R, C, G, K;  // side, sites, nominal R, capacity, groups, levels
     int32_t theta, resample, layout, max_steps;
+    int32_t update;            // PA_UPDATE_*
     uint32_t key0, key1;
     int32_t nblk;              // ceil(C / kSlotBlock)
     int32_t pad;

@@ -32,6 +32,7 @@ struct LaunchCtx {
     std::vector<SweepClass> sweep_classes;  // one launch per distinct L
     bool any_nearest, any_multi, any_poisson;
     bool any_msc, any_int8;  // layouts present in the batch
+    bool any_update[2];      // spin-update rules present in the batch (PA_UPDATE_*)
 };
 
 hipError_t configure_kernels();

@@ -179,7 +179,8 @@ __global__ void __launch_bounds__(256) k_hist(const RunDesc *runs, WorkMap map) 
 // boundary aborts the run with PA_ERR_NUMERIC.  dB = 0 or a single occupied
 // level make every w_l = 1 and S = R_{i-1} exactly; those use integer math.
 // Also: the Metropolis thresholds t4 = ceil(2^32 e^{-4 beta_i}), t8 =
-// ceil(2^32 e^{-8 beta_i}) and the end-of-schedule check.
+// ceil(2^32 e^{-8 beta_i}) (heatbath: floor(2^32 / (1 + e^{4 beta_i})) and
+// floor(2^32 / (1 + e^{8 beta_i}))) and the end-of-schedule check.
 constexpr double kPoissonMaxMean = 65536.0;  // largest supported tau_hat
 constexpr int kPoissonMax = 1 << 18;          // > kPoissonMaxMean + 40 sqrt(kPoissonMaxMean)
 constexpr double kPoissonMargin = 0x1p-8;     // in units of U
@@ -214,7 +215,22 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     if (threadIdx.x == last) {
         const double b1 = rd.betas[i];
         if (b1 == 0.0) {
-            st->t4 = st->t8 = 1ull << 32;
+            st->t4 = st->t8 = 1ull << 32;  // heatbath: every flip has probability 1/2
+        } else if (rd.update == PA_UPDATE_HEATBATH) {
+            // T'_dE = floor(2^32 q / (1 + q)), q = e^{-beta dE}, dE = 4, 8: the
+            // dE > 0 classes flip iff u <= T', the dE < 0 classes iff ~u >= T'
+            dd q4;
+            bool amb = false;
+            if (!dd_exp_neg(dd{4.0 * b1, 0.0}, &q4)) {
+                st->t4 = st->t8 = 0;  // q < 2^-1000
+            } else {
+                const dd q8 = dd_mul(q4, q4);
+                const dd p4 = dd_div(q4, dd_add(dd{1.0, 0.0}, q4));
+                const dd p8 = dd_div(q8, dd_add(dd{1.0, 0.0}, q8));
+                st->t4 = dd_floor_decided(dd_ldexp(p4, 32), &amb);
+                st->t8 = p8.hi < 0x1p-990 ? 0 : dd_floor_decided(dd_ldexp(p8, 32), &amb);
+            }
+            if (amb) atomicOr(&amb_any, 1);
         } else {
             dd p4;
             bool amb = false;
@@ -1183,6 +1199,225 @@ __device__ __forceinline__ void metropolis_words(const uint64_t (*nbr)[4], const
     }
 }
 
+// ------------------------------------------------------------------ heatbath
+
+// Heatbath (Sec. "Spin updates"): every move flips with probability
+// p(dE) = 1 / (1 + e^{beta dE}), i.e. iff u32 < T(dE) = ceil(2^32 p(dE)), for
+// the five classes dE = 8 - 4A (A antiparallel neighbours, 0..4).  For
+// beta > 0, 2^32 p is never an integer and p(-dE) = 1 - p(dE), so with
+// T' = T(|dE|) - 1 = floor(2^32 p(|dE|)):
+//   dE > 0: u < T(dE)   iff  u <= T'
+//   dE < 0: u < T(dE) = 2^32 + 1 - T(|dE|)   iff  ~u >= T'
+//   dE = 0: u < 2^31    iff  the top bit of u is 0.
+// The dE = +-4 classes share T'_4 and the +-8 classes T'_8, so a plane step
+// compares the plane bit with t* = t ^ neg, t = T'_4's or T'_8's bit by the
+// lane's |dE| and neg the dE < 0 lanes: the lane is decided where its bit
+// differs from t*, and flips iff that bit is 0 (for dE > 0 a 0 below a 1 of
+// T' means u < T'; for dE < 0 a 0 of u is a 1 of ~u above a 0 of T').
+// A lane whose top six bits leave its comparison open draws 26 fresh bits
+// (ties as in the Metropolis comparison); "open" is a property of the
+// comparison itself, so it is the same set whichever way it is written.
+// Classes per 32-bit half: x = a1 ^ a2 ^ a3, m = maj(a1, a2, a3), A = x + a4 + 2m:
+//   |dE| = 4 (A odd): x ^ a4;  dE < 0 (A >= 3): m & (x | a4);  dE = 0 (A = 2):
+//   (m & ~x & ~a4) | (~m & x & a4).
+struct HbClass {
+    uint32_t mag4, neg, x4, zero;
+};
+__device__ __forceinline__ HbClass hb_class(uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4) {
+    const uint32_t x = __builtin_amdgcn_bitop3_b32(a1, a2, a3, 0x96);  // xor3
+    const uint32_t m = __builtin_amdgcn_bitop3_b32(a1, a2, a3, 0xE8);  // maj
+    HbClass c;
+    c.mag4 = x ^ a4;
+    c.neg = __builtin_amdgcn_bitop3_b32(m, x, a4, 0xE0);   // m & (x | a4)
+    c.zero = __builtin_amdgcn_bitop3_b32(m, x, a4, 0x18);  // A = 2
+    c.x4 = c.mag4 ^ c.neg;
+    return c;
+}
+
+// One plane on one half: t* = neg (threshold bits 0, 0), ~neg (1, 1), x4 =
+// mag4 ^ neg (T'_4 bit 1, T'_8 bit 0) or ~x4 (0, 1).
+template <int B4, int B8>
+__device__ __forceinline__ void hb_plane_half(uint32_t &und, uint32_t &flip, uint32_t neg, uint32_t x4,
+                                              uint32_t pl) {
+    constexpr bool same = B4 == B8;
+    constexpr bool inv = same ? (B4 != 0) : (B4 == 0);
+    const uint32_t X = same ? neg : x4;
+    const uint32_t acc = __builtin_amdgcn_bitop3_b32(und, X, pl, inv ? 0x10 : 0x40);  // und & t* & ~pl
+    und = __builtin_amdgcn_bitop3_b32(und, X, pl, inv ? 0x60 : 0x90);                // und & ~(t* ^ pl)
+    flip |= acc;
+}
+struct HbLanes {
+    uint32_t ul, uh, fl, fh;  // undecided and flipped lanes, low and high halves
+    HbClass cl, ch;
+};
+template <int C, int K>
+__device__ __forceinline__ void hb_pair_case(HbLanes *s, const U4 *x) {
+    constexpr int A4 = (C >> 3) & 1, A8 = (C >> 2) & 1, B4 = (C >> 1) & 1, B8 = C & 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        hb_plane_half<A4, A8>(s[k].ul, s[k].fl, s[k].cl.neg, s[k].cl.x4, x[k].x);
+        hb_plane_half<A4, A8>(s[k].uh, s[k].fh, s[k].ch.neg, s[k].ch.x4, x[k].y);
+        hb_plane_half<B4, B8>(s[k].ul, s[k].fl, s[k].cl.neg, s[k].cl.x4, x[k].z);
+        hb_plane_half<B4, B8>(s[k].uh, s[k].fh, s[k].ch.neg, s[k].ch.x4, x[k].w);
+    }
+}
+template <int K>
+__device__ __forceinline__ void hb_pair(HbLanes *s, uint32_t T4, uint32_t T8, uint32_t p, const U4 *x) {
+    const uint32_t sa = 31u - 2u * p, sb = 30u - 2u * p;
+    const uint32_t c = (((T4 >> sa) & 1u) << 3) | (((T8 >> sa) & 1u) << 2) |
+                       (((T4 >> sb) & 1u) << 1) | ((T8 >> sb) & 1u);
+    switch (c) {
+    case 0: hb_pair_case<0, K>(s, x); break;
+    case 1: hb_pair_case<1, K>(s, x); break;
+    case 2: hb_pair_case<2, K>(s, x); break;
+    case 3: hb_pair_case<3, K>(s, x); break;
+    case 4: hb_pair_case<4, K>(s, x); break;
+    case 5: hb_pair_case<5, K>(s, x); break;
+    case 6: hb_pair_case<6, K>(s, x); break;
+    case 7: hb_pair_case<7, K>(s, x); break;
+    case 8: hb_pair_case<8, K>(s, x); break;
+    case 9: hb_pair_case<9, K>(s, x); break;
+    case 10: hb_pair_case<10, K>(s, x); break;
+    case 11: hb_pair_case<11, K>(s, x); break;
+    case 12: hb_pair_case<12, K>(s, x); break;
+    case 13: hb_pair_case<13, K>(s, x); break;
+    case 14: hb_pair_case<14, K>(s, x); break;
+    default: hb_pair_case<15, K>(s, x); break;
+    }
+}
+
+// Tie thresholds on the fresh word v (its top 26 bits are the lane's low 26):
+// dE > 0 flips iff (v >> 6) <= low26(T'), i.e. v < (low26(T') + 1) << 6;
+// dE < 0 flips iff (v >> 6) <= 2^26 - 1 - low26(T'), i.e. v < (2^26 - low26(T')) << 6.
+// A class whose bound would be 2^32 (low26(T') = 2^26 - 1 for dE > 0, 0 for
+// dE < 0) never ties: equal top bits already decide it (hb_settle).
+struct HbTie {
+    uint32_t p4, n4, p8, n8;
+};
+__device__ __forceinline__ HbTie hb_tie_bounds(uint32_t T4, uint32_t T8) {
+    const uint32_t l4 = T4 & 0x3FFFFFFu, l8 = T8 & 0x3FFFFFFu;
+    return HbTie{(l4 + 1u) << 6, (0x4000000u - l4) << 6, (l8 + 1u) << 6, (0x4000000u - l8) << 6};
+}
+// Lanes still tied after six planes whose comparison those bits already
+// decide (see HbTie) flip now; only needed when hb_needs_settle.
+__device__ __forceinline__ bool hb_needs_settle(uint32_t T4, uint32_t T8) {
+    const uint32_t l4 = T4 & 0x3FFFFFFu, l8 = T8 & 0x3FFFFFFu;
+    return l4 == 0x3FFFFFFu || l4 == 0u || l8 == 0x3FFFFFFu || l8 == 0u;
+}
+__device__ __forceinline__ void hb_settle(uint64_t &und, uint64_t &flip, uint64_t mag4, uint64_t neg,
+                                          uint32_t T4, uint32_t T8) {
+    const uint32_t l4 = T4 & 0x3FFFFFFu, l8 = T8 & 0x3FFFFFFu;
+    uint64_t sel = 0;
+    if (l4 == 0x3FFFFFFu) sel |= mag4 & ~neg;
+    if (l4 == 0u) sel |= mag4 & neg;
+    if (l8 == 0x3FFFFFFu) sel |= ~mag4 & ~neg;
+    if (l8 == 0u) sel |= ~mag4 & neg;
+    sel &= und;
+    flip |= sel;
+    und &= ~sel;
+}
+__device__ __forceinline__ void hb_tie_one(uint64_t &und, uint64_t mag4, uint64_t neg, const HbTie &b,
+                                           uint32_t v, uint64_t &flip) {
+    const uint64_t bit = und & (0ull - und);  // lowest tied lane; 0 when none is left
+    und ^= bit;
+    const uint32_t mp4 = v < b.p4 ? ~0u : 0u, mn4 = v < b.n4 ? ~0u : 0u;
+    const uint32_t mp8 = v < b.p8 ? ~0u : 0u, mn8 = v < b.n8 ? ~0u : 0u;
+    uint32_t a[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const uint32_t m4 = (uint32_t)(mag4 >> (32 * hh)), ng = (uint32_t)(neg >> (32 * hh));
+        const uint32_t ap = __builtin_amdgcn_bitop3_b32(m4, mp4, mp8, 0xCA);  // mag4 ? mp4 : mp8
+        const uint32_t an = __builtin_amdgcn_bitop3_b32(m4, mn4, mn8, 0xCA);
+        a[hh] = __builtin_amdgcn_bitop3_b32(ng, an, ap, 0xCA);
+    }
+    flip = ((uint64_t)(uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(flip >> 32), (uint32_t)(bit >> 32),
+                                                             a[1], 0xF8) << 32) |
+           (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)flip, (uint32_t)bit, a[0], 0xF8);
+}
+__device__ __forceinline__ void hb_tie_call(uint64_t &und, uint64_t mag4, uint64_t neg, const HbTie &b,
+                                            const U4 &x, uint64_t &flip) {
+    hb_tie_one(und, mag4, neg, b, x.x, flip);
+    if (und == 0) return;
+    hb_tie_one(und, mag4, neg, b, x.y, flip);
+    if (und == 0) return;
+    hb_tie_one(und, mag4, neg, b, x.z, flip);
+    hb_tie_one(und, mag4, neg, b, x.w, flip);
+}
+
+// K words of one lane (as metropolis_words).  T4, T8: T'_4, T'_8; coin: beta
+// = 0, where every move flips iff the top bit of u is 0; settle:
+// hb_needs_settle(T4, T8) (uniform).  Calls are counted as in metropolis_word.
+template <int K>
+__device__ __forceinline__ void heatbath_words(const uint64_t (*nbr)[4], const uint64_t *s0,
+                                               const uint64_t *valid, uint32_t T4, uint32_t T8,
+                                               bool coin, bool settle, uint32_t k0, uint32_t k1,
+                                               const uint32_t *w, const uint32_t *g, uint32_t h,
+                                               uint64_t *flip, bool count, uint32_t *calls,
+                                               uint32_t *wcalls) {
+    HbLanes s[K];
+    uint32_t zl[K], zh[K];  // dE = 0 lanes (every lane when coin), decided by plane 0
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint64_t a1 = s0[k] ^ nbr[k][0], a2 = s0[k] ^ nbr[k][1], a3 = s0[k] ^ nbr[k][2],
+                       a4 = s0[k] ^ nbr[k][3];
+        s[k].cl = hb_class((uint32_t)a1, (uint32_t)a2, (uint32_t)a3, (uint32_t)a4);
+        s[k].ch = hb_class((uint32_t)(a1 >> 32), (uint32_t)(a2 >> 32), (uint32_t)(a3 >> 32),
+                           (uint32_t)(a4 >> 32));
+        const uint32_t vl = (uint32_t)valid[k], vh = (uint32_t)(valid[k] >> 32);
+        zl[k] = coin ? vl : vl & s[k].cl.zero;
+        zh[k] = coin ? vh : vh & s[k].ch.zero;
+        s[k].ul = vl & ~zl[k];
+        s[k].uh = vh & ~zh[k];
+        s[k].fl = s[k].fh = 0;
+    }
+#pragma unroll
+    for (uint32_t p = 0; p < kPlanePairs; ++p) {
+        U4 x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (count) {
+                const uint32_t need = p == 0 ? (s[k].ul | s[k].uh | zl[k] | zh[k]) : (s[k].ul | s[k].uh);
+                *wcalls += (uint32_t)__popcll(__ballot(need != 0));
+            }
+            x[k] = philox(k0, k1, w[k], g[k], h, kTagSweep | p);
+            if (p == 0) {  // dE = 0: u < 2^31
+                s[k].fl |= zl[k] & ~x[k].x;
+                s[k].fh |= zh[k] & ~x[k].y;
+            }
+        }
+        hb_pair<K>(s, T4, T8, p, x);
+    }
+    const HbTie tb = hb_tie_bounds(T4, T8);
+    uint64_t und[K], mag4[K], neg[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        und[k] = ((uint64_t)s[k].uh << 32) | s[k].ul;
+        flip[k] = ((uint64_t)s[k].fh << 32) | s[k].fl;
+        mag4[k] = ((uint64_t)s[k].ch.mag4 << 32) | s[k].cl.mag4;
+        neg[k] = ((uint64_t)s[k].ch.neg << 32) | s[k].cl.neg;
+        if (settle) {
+            // a real (uniform) branch: the compiler would otherwise evaluate
+            // the rarely needed selection for every word
+            asm volatile("");
+            hb_settle(und[k], flip[k], mag4[k], neg[k], T4, T8);
+        }
+    }
+    for (uint32_t q = 0;; ++q) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            any |= und[k] != 0;
+            *calls += und[k] != 0 ? 1u : 0u;  // read only when counting
+        }
+        if (!any) break;
+        U4 x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = philox(k0, k1, w[k], g[k], h, kTagTie | q);
+#pragma unroll
+        for (int k = 0; k < K; ++k) hb_tie_call(und[k], mag4[k], neg[k], tb, x[k], flip[k]);
+    }
+}
+
 // The block's lattices in LDS carry a halo: group gl's site (x, y) is word
 // gl A + (y + 1) P + x + 1 with row pitch P = L + 2 and A = (L + 2) P words
 // per group, and the ghost columns x = -1, L and rows y = -1, L hold copies
@@ -1354,7 +1589,26 @@ struct MeasCounters {
 constexpr int kMaxGroupsPerBlock = 8;
 constexpr int kWalkAny = 0, kWalkRows = 1, kWalkOneGroup = 2;
 
-template <int LAYOUT, int WALK, int ILP>
+// One word update of either rule (Metropolis, or heatbath when UPD; for
+// heatbath all4 is the beta = 0 flag and all8 the settle flag).
+template <int UPD>
+__device__ __forceinline__ uint64_t update_word(uint64_t s0, uint64_t n0, uint64_t n1, uint64_t n2,
+                                                uint64_t n3, uint64_t valid, uint32_t T4, uint32_t T8,
+                                                bool all4, bool all8, uint32_t k0, uint32_t k1,
+                                                uint32_t w, uint32_t g, uint32_t h, bool count,
+                                                uint32_t *calls, uint32_t *wcalls) {
+    if (UPD == PA_UPDATE_HEATBATH) {
+        const uint64_t nbr[1][4] = {{n0, n1, n2, n3}};
+        uint64_t f;
+        heatbath_words<1>(nbr, &s0, &valid, T4, T8, all4, all8, k0, k1, &w, &g, h, &f, count, calls,
+                          wcalls);
+        return f;
+    }
+    return metropolis_word(s0 ^ n0, s0 ^ n1, s0 ^ n2, s0 ^ n3, valid, T4, T8, all4, all8, k0, k1, w, g,
+                           h, count, calls, wcalls);
+}
+
+template <int LAYOUT, int WALK, int ILP, int UPD>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ILP == 1 ? 8 : 4)))
 k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     extern __shared__ uint64_t lat[];
@@ -1362,7 +1616,7 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     int bi;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &bi)];
     RunState *st = rd.st;
-    if (rd.layout != LAYOUT || st->err) return;
+    if (rd.layout != LAYOUT || rd.update != UPD || st->err) return;
     const int Rn = st->R_new;
     const int g0 = bi * gpb;
     if (g0 * kLanes >= Rn) return;
@@ -1416,7 +1670,10 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     const int theta = init ? 0 : rd.theta;
     const int i = st->step + 1;
     const uint64_t t4 = st->t4, t8 = st->t8;
-    const bool all4 = t4 >= (1ull << 32), all8 = t8 >= (1ull << 32);
+    // heatbath: all4 marks beta = 0 (fair coins) and all8 the settle flag
+    const bool all4 = t4 >= (1ull << 32);
+    const bool all8 = UPD == PA_UPDATE_HEATBATH ? hb_needs_settle((uint32_t)t4, (uint32_t)t8)
+                                                : t8 >= (1ull << 32);
     // the thresholds are the same for every lane: keep their bits in scalar registers
     const uint32_t T4 = __builtin_amdgcn_readfirstlane((uint32_t)t4);
     const uint32_t T8 = __builtin_amdgcn_readfirstlane((uint32_t)t8);
@@ -1444,11 +1701,10 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
                 for (int w = tid; w < words; w += nt) {
                     const int site = site1;
                     const uint64_t s0 = lat[site];
-                    const uint64_t f = metropolis_word(s0 ^ lat[site + 1], s0 ^ lat[site - 1],
-                                                       s0 ^ lat[site - P], s0 ^ lat[site + P],
-                                                       last_valid, T4, T8, all4, all8, k0, k1,
-                                                       (uint32_t)w, (uint32_t)g0, h, count, &calls,
-                                                       &wcalls);
+                    const uint64_t f = update_word<UPD>(s0, lat[site + 1], lat[site - 1], lat[site - P],
+                                                        lat[site + P], last_valid, T4, T8, all4, all8,
+                                                        k0, k1, (uint32_t)w, (uint32_t)g0, h, count,
+                                                        &calls, &wcalls);
                     lat[site] = s0 ^ f;
                     advance1();
                 }
@@ -1458,12 +1714,11 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
                     const int site = wk.row + x;
                     const uint64_t s0 = lat[site];
                     const uint64_t valid = wk.gl == ng - 1 ? last_valid : ~0ull;
-                    const uint64_t f = metropolis_word(s0 ^ lat[site + 1], s0 ^ lat[site - 1],
-                                                       s0 ^ lat[site - P], s0 ^ lat[site + P], valid,
-                                                       T4, T8, all4, all8, k0, k1,
-                                                       (uint32_t)(wk.y * half + wk.xh),
-                                                       (uint32_t)(g0 + wk.gl), h, count, &calls,
-                                                       &wcalls);
+                    const uint64_t f = update_word<UPD>(s0, lat[site + 1], lat[site - 1], lat[site - P],
+                                                        lat[site + P], valid, T4, T8, all4, all8, k0,
+                                                        k1, (uint32_t)(wk.y * half + wk.xh),
+                                                        (uint32_t)(g0 + wk.gl), h, count, &calls,
+                                                        &wcalls);
                     lat[site] = s0 ^ f;
                     if (WALK == kWalkRows)
                         walk_advance_rows(wk, step);
@@ -1502,8 +1757,12 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
                         nbr[k][2] = lat[site[k] - P];
                         nbr[k][3] = lat[site[k] + P];
                     }
-                    metropolis_words<ILP>(nbr, s0, valid, T4, T8, all4, all8, k0, k1, wi, gi, h, f,
-                                          count, &calls, &wcalls);
+                    if (UPD == PA_UPDATE_HEATBATH)
+                        heatbath_words<ILP>(nbr, s0, valid, T4, T8, all4, all8, k0, k1, wi, gi, h, f,
+                                            count, &calls, &wcalls);
+                    else
+                        metropolis_words<ILP>(nbr, s0, valid, T4, T8, all4, all8, k0, k1, wi, gi, h, f,
+                                              count, &calls, &wcalls);
 #pragma unroll
                     for (int k = 0; k < ILP; ++k)
                         if (f[k]) lat[site[k]] = s0[k] ^ f[k];
@@ -1992,15 +2251,22 @@ hipError_t launch_init(const LaunchCtx &c) {
 size_t sweep_lds_bytes(int L, int gpb) { return (size_t)gpb * (L + 2) * (L + 2) * 8; }
 
 // k_sweep instantiation for a layout, a word walk and words per thread at once
-static const void *sweep_kernel(int layout, int walk, int ilp) {
+template <int UPD>
+static const void *sweep_kernel_of(int layout, int walk, int ilp) {
     static const void *const fns[2][3][2] = {
-        {{(const void *)k_sweep<0, kWalkAny, 1>, (const void *)k_sweep<0, kWalkAny, 2>},
-         {(const void *)k_sweep<0, kWalkRows, 1>, (const void *)k_sweep<0, kWalkRows, 2>},
-         {(const void *)k_sweep<0, kWalkOneGroup, 1>, (const void *)k_sweep<0, kWalkOneGroup, 2>}},
-        {{(const void *)k_sweep<1, kWalkAny, 1>, (const void *)k_sweep<1, kWalkAny, 2>},
-         {(const void *)k_sweep<1, kWalkRows, 1>, (const void *)k_sweep<1, kWalkRows, 2>},
-         {(const void *)k_sweep<1, kWalkOneGroup, 1>, (const void *)k_sweep<1, kWalkOneGroup, 2>}}};
+        {{(const void *)k_sweep<0, kWalkAny, 1, UPD>, (const void *)k_sweep<0, kWalkAny, 2, UPD>},
+         {(const void *)k_sweep<0, kWalkRows, 1, UPD>, (const void *)k_sweep<0, kWalkRows, 2, UPD>},
+         {(const void *)k_sweep<0, kWalkOneGroup, 1, UPD>,
+          (const void *)k_sweep<0, kWalkOneGroup, 2, UPD>}},
+        {{(const void *)k_sweep<1, kWalkAny, 1, UPD>, (const void *)k_sweep<1, kWalkAny, 2, UPD>},
+         {(const void *)k_sweep<1, kWalkRows, 1, UPD>, (const void *)k_sweep<1, kWalkRows, 2, UPD>},
+         {(const void *)k_sweep<1, kWalkOneGroup, 1, UPD>,
+          (const void *)k_sweep<1, kWalkOneGroup, 2, UPD>}}};
     return fns[layout][walk][ilp - 1];
+}
+static const void *sweep_kernel(int layout, int walk, int ilp, int upd) {
+    return upd == PA_UPDATE_HEATBATH ? sweep_kernel_of<PA_UPDATE_HEATBATH>(layout, walk, ilp)
+                                     : sweep_kernel_of<PA_UPDATE_METROPOLIS>(layout, walk, ilp);
 }
 
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
@@ -2012,10 +2278,13 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init) {
         const int ilp = lds > kMaxSweepLds / 2 ? 2 : 1;
         for (int layout = 0; layout < 2; ++layout) {
             if (!(layout == PA_LAYOUT_MSC64 ? cls.has_msc : cls.has_int8)) continue;
-            const void *fn = sweep_kernel(layout, walk, ilp);
-            void *args[] = {(void *)&c.runs, (void *)&cls.map, (void *)&init, (void *)&cls.gpb};
-            hipError_t e = hipLaunchKernel(fn, dim3(cls.total), dim3(cls.threads), args, lds, c.stream);
-            if (e != hipSuccess) return e;
+            for (int upd = 0; upd < 2; ++upd) {
+                if (!c.any_update[upd]) continue;
+                const void *fn = sweep_kernel(layout, walk, ilp, upd);
+                void *args[] = {(void *)&c.runs, (void *)&cls.map, (void *)&init, (void *)&cls.gpb};
+                hipError_t e = hipLaunchKernel(fn, dim3(cls.total), dim3(cls.threads), args, lds, c.stream);
+                if (e != hipSuccess) return e;
+            }
         }
     }
     return hipSuccess;
@@ -2128,8 +2397,8 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 
 hipError_t configure_kernels() {
     // up to kMaxSweepLds bytes of lattices (with their halo) per sweep block
-    for (int k = 0; k < 12; ++k) {
-        const void *f = sweep_kernel(k / 6, (k / 2) % 3, k % 2 + 1);
+    for (int k = 0; k < 24; ++k) {
+        const void *f = sweep_kernel((k / 6) & 1, (k / 2) % 3, k % 2 + 1, k / 12);
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
         if (e != hipSuccess) return e;
     }

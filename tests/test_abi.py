@@ -66,13 +66,16 @@ def test_workspace_size_scales_with_layout_and_population():
 
 
 @pytest.mark.parametrize("bad", [dict(L=7), dict(L=2), dict(L=130), dict(R=0), dict(theta=-1),
-                                 dict(resample="bogus"), dict(capacity=10),
+                                 dict(resample="bogus"), dict(update="bogus"), dict(capacity=10),
                                  dict(betas=[0.1, 0.2]), dict(betas=[0.0, 0.3, 0.2]),
                                  dict(betas=[0.0, float("nan")])])
 def test_invalid_configurations_are_rejected(bad):
     if bad.get("resample") == "bogus":
         cfg, arr = _cfg()
         cfg.resample = 7
+    elif bad.get("update") == "bogus":
+        cfg, arr = _cfg()
+        cfg.update = 2
     else:
         cfg, arr = _cfg(**bad)
     st, _ = _ws(cfg)

@@ -237,12 +237,13 @@ GEOMETRIES = {
 }
 
 
+@pytest.mark.parametrize("update", ["metropolis", "heatbath"])
 @pytest.mark.parametrize("L", sorted(GEOMETRIES))
-def test_sweep_geometry_does_not_change_results(L):
+def test_sweep_geometry_does_not_change_results(L, update):
     betas = linear_schedule(0.5, 4)
     states = []
     for threads, gpb in GEOMETRIES[L]:
-        r = pa.Run(L, 1000, betas, 3, 61, "nearest", "msc64")
+        r = pa.Run(L, 1000, betas, 3, 61, "nearest", "msc64", update=update)
         r.set_sweep_launch(L, threads, gpb)
         assert r.sweep_launch(L) == (threads, gpb, 0)
         r.run(4)

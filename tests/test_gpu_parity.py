@@ -253,6 +253,47 @@ def test_capacity_overflow_is_reported_and_state_kept():
     assert len(ref.E) > 128  # the step that overflowed
 
 
+HEATBATH_CASES = [
+    # L, R, theta, betas, resample, layout
+    (8, 200, 3, linear_schedule(0.44, 8), "nearest", "msc64"),
+    (8, 200, 3, linear_schedule(0.44, 8), "nearest", "int8"),
+    (6, 130, 2, linear_schedule(0.6, 6), "multinomial", "int8"),
+    (4, 64, 5, linear_schedule(1.2, 10), "poisson", "msc64"),
+    (12, 100, 2, linear_schedule(3.0, 4), "none", "msc64"),  # large beta: small T'
+    (10, 1, 2, linear_schedule(0.5, 5), "nearest", "msc64"),
+    (16, 150, 2, [0.0, 0.0, 0.0, 0.2, 0.4], "nearest", "msc64"),  # beta = 0: fair coins
+]
+
+
+@pytest.mark.parametrize("L,R,theta,betas,resample,layout", HEATBATH_CASES)
+def test_heatbath_run_parity_step_by_step(L, R, theta, betas, resample, layout):
+    log("heatbath parity", L, R, theta, betas[-1], resample, layout)
+    n = len(betas) - 1
+    run = pa.Run(L, R, betas, theta, PARITY_SEED, resample, layout, update="heatbath")
+    ref = po.OracleRun(L, R, theta, PARITY_SEED, resample, betas, update="heatbath")
+    for i in range(1, n + 1):
+        run.anneal_step()
+        ref.anneal_step()
+        check_record(run.observables(i), ref.records[i], "step %d" % i)
+        assert np.array_equal(run.copy_counts(), ref.last_counts), i
+        check_population(run, ref, "step %d" % i)
+    run.close()
+
+
+def test_update_rules_differ_and_snapshots_keep_the_rule():
+    betas = linear_schedule(0.44, 3)
+    a = pa.Run(8, 128, betas, 2, 3, "nearest", "msc64")
+    b = pa.Run(8, 128, betas, 2, 3, "nearest", "msc64", update="heatbath")
+    a.run(3)
+    b.run(3)
+    assert not np.array_equal(a.population()[0], b.population()[0])
+    with pytest.raises(pa.PAError) as ei:
+        b.set_state(a.get_state())
+    assert ei.value.status == pa.PA_ERR_STATE
+    a.close()
+    b.close()
+
+
 def test_extinct_population_is_reported():
     # R = 2, Poisson: for some seeds both parents draw zero copies at step 1
     # (seeds 27 and 35 among 20..39); the device reports PA_ERR_EXTINCT
@@ -291,12 +332,13 @@ def test_schedule_end_is_reported():
     run.sync()
 
 
-def _sampled_step_parity(L, R, resample, layout, n_steps, beta_f, k, theta, seed, n_groups=6):
+def _sampled_step_parity(L, R, resample, layout, n_steps, beta_f, k, theta, seed, n_groups=6,
+                         update="metropolis"):
     """GPU step k -> k+1 at full size; the oracle recomputes the copy counts of
     all parents and the sweeps of a sample of replica groups."""
     betas = linear_schedule(beta_f, n_steps)
     s = torch.cuda.Stream()
-    run = pa.Run(L, R, betas, theta, seed, resample, layout, stream=s)
+    run = pa.Run(L, R, betas, theta, seed, resample, layout, stream=s, update=update)
     run.run(k)
     run.sync()
     snap_spins, snap_fam, snap_E, _ = run.population()
@@ -318,11 +360,15 @@ def _sampled_step_parity(L, R, resample, layout, n_steps, beta_f, k, theta, seed
     rng = np.random.default_rng(seed)
     groups = sorted(set([0, G - 1] + list(rng.integers(0, G, n_groups))))
     t4, t8 = po.metropolis_threshold(betas[k + 1], 4), po.metropolis_threshold(betas[k + 1], 8)
+    thr5 = [po.heatbath_threshold(betas[k + 1], dE) for dE in (-8, -4, 0, 4, 8)]
     for g in groups:
         lo, hi = 64 * g, min(64 * g + 64, R_new)
         parents = np.searchsorted(off, np.arange(lo, hi), side="right") - 1
         kids = np.ascontiguousarray(snap_spins[parents])
-        po.sweeps(seed, L, kids, k + 1, theta, t4, t8, slot0=lo)
+        if update == "heatbath":
+            po.sweeps_heatbath(seed, L, kids, k + 1, theta, thr5, slot0=lo)
+        else:
+            po.sweeps(seed, L, kids, k + 1, theta, t4, t8, slot0=lo)
         E, M = po.energy_magnetisation(L, kids)
         gs, gf, gE, gM = run.population(lo, hi - lo)
         assert np.array_equal(gs, kids), g
@@ -337,6 +383,17 @@ def test_l64_multinomial_sampled_step_parity(layout):
     """L=64, R=100000, multinomial, beta 0 -> 0.4407 in 200 steps: step 120 -> 121."""
     log("L64 sampled", layout)
     _sampled_step_parity(64, 100_000, "multinomial", layout, 200, 0.4407, 120, 10, PARITY_SEED)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("L,k", [(64, 120), (128, 180)])
+def test_heatbath_sampled_step_parity(L, k):
+    """Heatbath at full size: L=64 (one group per block, one word per thread)
+    and L=128 (two words per thread), R=100000, nearest."""
+    log("heatbath sampled", L)
+    n, bf = (200, 0.4407) if L == 64 else (400, 1.0)
+    _sampled_step_parity(L, 100_000, "nearest", "msc64", n, bf, k, 10, PARITY_SEED, 3,
+                         update="heatbath")
 
 
 @pytest.mark.slow
