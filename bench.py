@@ -128,6 +128,38 @@ def time_batch(pa, torch, K):
                         "nearest, multispin, beta 0->0.4407 in 200 steps, theta=10, one HIP graph per step"}
 
 
+def time_weighted(pa, torch, M=64, L=32, R=2000, n=200):
+    """Weighted averages over M runs sharing one schedule (pa_batch_weighted),
+    all n + 1 steps in one call, timed by wall clock (the call also checks
+    every run's state on the host)."""
+    import ctypes
+    from workloads import linear_schedule
+    betas = linear_schedule(0.4407, n)
+    specs = [dict(L=L, R=R, theta=THETA, seed=2000 + m, resample="nearest", layout="msc64",
+                  betas=betas) for m in range(M)]
+    b = pa.Batch(specs)
+    b.run(n)
+    b.sync()
+    out = torch.empty((n + 1) * ctypes.sizeof(pa.pa_weighted), dtype=torch.uint8, device="cuda")
+    call = lambda: pa._check(pa.lib().pa_batch_weighted(b.h, 0, n + 1, ctypes.c_void_p(out.data_ptr())),
+                             b.h, batch=True)
+    for _ in range(3):  # warm
+        call()
+    b.sync()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    b.sync()
+    wall = (time.perf_counter() - t0) / reps
+    last = b.weighted(n)[0]
+    b.close()
+    return {"runs": M, "L": L, "R": R, "steps": n + 1,
+            "us_per_call_all_steps": wall * 1e6,
+            "at_last_step": {k: last[k] for k in ("e", "e_plain", "c_v", "c_v_plain", "n_eff_runs",
+                                                  "var_beta_F", "rho_f", "cov_e")}}
+
+
 def cpu_baseline(betas, energies):
     """The oracle, single-threaded, on a bounded sample of the same workload.
 
@@ -249,6 +281,20 @@ def main():
             "blocking_last": {k: recs[-1][k] for k in ("r_eff_E", "r_eff_absM", "err_e")},
             "sweep_geometry": prof["geometry"],
         }
+        # overlap correlation C_q(d), d <= 1024, of the final population (events on
+        # the run's stream; the call first reads the run state on the host)
+        import torch as _t
+        s_ = run.stream
+        run.overlap_correlation(1024)
+        e0, e1 = _t.cuda.Event(enable_timing=True), _t.cuda.Event(enable_timing=True)
+        e0.record(s_)
+        cq = run.overlap_correlation(1024)
+        e1.record(s_)
+        e1.synchronize()
+        results[layout]["overlap_correlation"] = {
+            "d_max": 1024, "us": e0.elapsed_time(e1) * 1e3,
+            "pair_words_per_us": (L * L) * (R / 64) * 1024 / (e0.elapsed_time(e1) * 1e3),
+            "C_q": {str(d): float(cq[d]) for d in (1, 2, 4, 16, 64, 256, 1024)}}
         if layout == head_candidate(args.layouts) and not args.no_cpu_baseline:
             # energies entering step 101, for the CPU-baseline resampling sample
             e_run = pa.Run(L, R, betas, THETA, SEED, "multinomial", layout)
@@ -309,6 +355,9 @@ def main():
         torch.cuda.empty_cache()
         log("timing the 64-run batch: 200 steps")
         extra["batched_64_runs"] = time_batch(pa, torch, 200)
+        torch.cuda.empty_cache()
+        log("timing the combination of 64 independent runs (L=32, R=2000, nearest): 200 steps")
+        extra["runs_combined"] = time_weighted(pa, torch)
         torch.cuda.empty_cache()
 
     head_layout = "msc64" if "msc64" in results else list(results)[0]

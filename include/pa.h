@@ -255,6 +255,51 @@ pa_status pa_batch_set_sweep_launch(pa_batch *b, int32_t L, int32_t threads,
                                     int32_t groups_per_block, int32_t variant);
 pa_status pa_batch_get_sweep_launch(pa_batch *b, int32_t L, int32_t *threads,
                                     int32_t *groups_per_block, int32_t *variant);
+
+/* Overlap correlation of the current population along its index (Sec.
+ * "Effective population size", Eq. overlap_correlation): with copies of one
+ * parent at adjacent indices, C_q(d) = sum_{i < R_i - d} sum_k s_k^(i)
+ * s_k^(i+d) / (N (R_i - d)), the mean overlap of the R_i - d pairs at index
+ * distance d, for d = 0 .. d_max (C_q(0) = 1) into dev_cq (device memory,
+ * d_max + 1 doubles), asynchronously on the run's stream.  It waits for the
+ * queued steps to read R_i; 1 <= d_max <= min(R_i - 1, 65536), PA_ERR_ARG
+ * otherwise.  The sums over pairs are exact integers. */
+pa_status pa_overlap_correlation(pa_ctx *ctx, int32_t d_max, double *dev_cq);
+
+/* Combination of the batch's independent runs at one temperature (Sec.
+ * "Weighted averages", Eqs. weighted-averages and modified-weights2; Sec.
+ * "Bias with resampling", Eqs. bias_covariance and rho_f).  Each run m
+ * contributes its thermal averages <E>, <E^2>, <|M|>, <M^2> at step i (from
+ * its exact population sums) with weight
+ *   omega_i^m = R_i^m e^{-beta_i F_i^m} / sum_m' (same)           (weighted-averages)
+ * or, for a fluctuating population, with the extra factor
+ *   prod_{k=1}^{i} R_{k-1}^m / R^m, R^m the run's nominal size     (modified-weights2);
+ * e = <E>/N, m = <|M|>/N, c_v = beta^2 (<E^2> - <E>^2)/N and chi = beta
+ * (<M^2> - <|M|>^2)/N are formed from the combined averages.  The plain
+ * average uses omega = 1/M.  The spread of the runs: sigma^2(beta F), the
+ * sample variance over the runs of beta_i F_i^m; rho_f = R sigma^2(beta F)
+ * with R the mean nominal size; cov_*: the sample covariance over the runs of
+ * each run's own e, m, c_v, chi with its beta_i F_i^m (the bias estimate). */
+typedef struct pa_weighted {
+    int32_t step;          /* i */
+    int32_t n_runs;        /* M; 0 when the runs do not share beta_i (every field NaN) */
+    double beta;           /* beta_i */
+    double e, m, c_v, chi;                          /* Eq. weighted-averages */
+    double e_mod, m_mod, c_v_mod, chi_mod;          /* Eq. modified-weights2 */
+    double e_plain, m_plain, c_v_plain, chi_plain;  /* omega = 1/M */
+    double omega_max;      /* largest omega_i^m of Eq. weighted-averages */
+    double n_eff_runs;     /* 1 / sum_m (omega_i^m)^2 */
+    double var_beta_F;     /* sigma^2(beta F) over the runs; NaN for M < 2 (so are rho_f, cov_*) */
+    double rho_f;          /* Eq. rho_f */
+    double cov_e, cov_m, cov_c_v, cov_chi;          /* Eq. bias_covariance */
+} pa_weighted;
+
+/* Steps first .. first + count - 1 of all runs of b, one pa_weighted each,
+ * into dev_out (device memory, count elements), asynchronously on the
+ * batch's stream.  The runs must have one lattice size L and have reached
+ * the last step (it waits for the queued steps to check this); PA_ERR_ARG
+ * otherwise, or for count < 1 or first < 0. */
+pa_status pa_batch_weighted(pa_batch *b, int32_t first, int32_t count, pa_weighted *dev_out);
 void pa_batch_destroy(pa_batch *b);
 const char *pa_batch_last_error(const pa_batch *b);
 

@@ -62,6 +62,14 @@ class pa_obs(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class pa_weighted(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int32), ("n_runs", ctypes.c_int32), ("beta", ctypes.c_double)] + \
+               [(n, ctypes.c_double) for n in (
+                   "e", "m", "c_v", "chi", "e_mod", "m_mod", "c_v_mod", "chi_mod", "e_plain",
+                   "m_plain", "c_v_plain", "chi_plain", "omega_max", "n_eff_runs", "var_beta_F",
+                   "rho_f", "cov_e", "cov_m", "cov_c_v", "cov_chi")]
+
+
 class PAError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
@@ -97,6 +105,8 @@ SIGNATURES = {
     "pa_batch_create": (_i32, [_P(pa_config), _i32, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "pa_batch_run": (_i32, [_vp, _i32]),
     "pa_batch_observables": (_i32, [_vp, _i32, _i32, _P(pa_obs)]),
+    "pa_batch_weighted": (_i32, [_vp, _i32, _i32, _vp]),
+    "pa_overlap_correlation": (_i32, [_vp, _i32, _vp]),
     "pa_batch_sync": (_i32, [_vp]),
     "pa_batch_destroy": (None, [_vp]),
     "pa_batch_last_error": (ctypes.c_char_p, [_vp]),
@@ -265,6 +275,15 @@ class Run:
     def set_state(self, blob: bytes):
         _check(lib().pa_set_state(self.h, blob, len(blob)), self.h)
 
+    def overlap_correlation(self, d_max: int) -> np.ndarray:
+        """C_q(d), d = 0 .. d_max, of the current population (pa_overlap_correlation)."""
+        import torch
+        dev = torch.empty(d_max + 1, dtype=torch.float64, device=self.workspace.device)
+        _check(lib().pa_overlap_correlation(self.h, int(d_max), ctypes.c_void_p(dev.data_ptr())),
+               self.h)
+        self.sync()
+        return dev.cpu().numpy()
+
     def overlap(self, dbeta: float) -> float:
         a = ctypes.c_double()
         _check(lib().pa_overlap(self.h, float(dbeta), ctypes.byref(a)), self.h)
@@ -378,6 +397,18 @@ class Batch:
         _check(lib().pa_batch_observables(self.h, int(run), int(step), ctypes.byref(o)), self.h,
                batch=True)
         return o.as_dict()
+
+    def weighted(self, first: int, count: int = 1) -> List[dict]:
+        """The runs combined at steps first .. first + count - 1 (pa_batch_weighted)."""
+        import torch
+        dev = torch.empty(count * ctypes.sizeof(pa_weighted), dtype=torch.uint8,
+                          device=self.workspace.device)
+        _check(lib().pa_batch_weighted(self.h, int(first), int(count),
+                                       ctypes.c_void_p(dev.data_ptr())), self.h, batch=True)
+        self.sync()
+        host = dev.cpu().numpy().tobytes()
+        arr = (pa_weighted * count).from_buffer_copy(host)
+        return [{k: getattr(w, k) for k, _ in pa_weighted._fields_} for w in arr]
 
     def close(self):
         if getattr(self, "h", None):

@@ -982,6 +982,40 @@ pa_status pa_batch_sync(pa_batch *b) {
     return engine_sync(b);
 }
 
+pa_status pa_overlap_correlation(pa_ctx *ctx, int32_t d_max, double *dev_cq) {
+    if (!ctx || !dev_cq) return fail(nullptr, PA_ERR_ARG, "bad arguments");
+    pa_batch *B = &ctx->b;
+    if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
+    RunState s;
+    pa_status e = read_state(B, 0, &s);
+    if (e) return e;
+    if (s.err) return fail(B, s.err, "the run stopped on a device status");
+    if (d_max < 1 || d_max >= s.R_cur || d_max > kMaxOverlapDistance)
+        return fail(B, PA_ERR_ARG, "d_max outside [1, min(R_i - 1, 65536)]");
+    PA_HIP(B, launch_overlap_correlation(B->lc, B->desc[0].N, s.R_cur, d_max, dev_cq));
+    return PA_OK;
+}
+
+pa_status pa_batch_weighted(pa_batch *b, int32_t first, int32_t count, pa_weighted *dev_out) {
+    if (!b) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    if (!dev_out || count < 1 || first < 0) return fail(b, PA_ERR_ARG, "bad arguments");
+    if (b->dead) return fail(b, PA_ERR_DEVICE, "handle is unusable after a device error");
+    const int last = first + count - 1;
+    if (last < first) return fail(b, PA_ERR_ARG, "bad arguments");
+    for (int r = 0; r < b->n; ++r) {
+        if (b->cfg[r].L != b->cfg[0].L) return fail(b, PA_ERR_ARG, "the runs differ in L");
+        RunState s;
+        pa_status e = read_state(b, r, &s);
+        if (e) return e;
+        if (last > s.step) {
+            if (s.err) return fail(b, s.err, "step not reached: a run stopped on a device status");
+            return fail(b, PA_ERR_ARG, "step not reached yet");
+        }
+    }
+    PA_HIP(b, launch_weighted(b->lc, first, count, dev_out));
+    return PA_OK;
+}
+
 void pa_batch_destroy(pa_batch *b) {
     if (!b) return;
     engine_destroy(b);

@@ -9,6 +9,8 @@
 
 namespace pa {
 
+constexpr int kMaxOverlapDistance = 65536;  // largest d of pa_overlap_correlation
+
 struct MapInfo {
     WorkMap map;  // device arrays
     int total;    // blocks in the launch
@@ -43,6 +45,8 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init);
 hipError_t launch_reduce(const LaunchCtx &c);
 hipError_t launch_step(const LaunchCtx &c);
 hipError_t launch_counts(const LaunchCtx &c);  // reweighting, copy counts, offsets
+hipError_t launch_weighted(const LaunchCtx &c, int first, int count, pa_weighted *out);
+hipError_t launch_overlap_correlation(const LaunchCtx &c, int N, int R, int d_max, double *cq);
 hipError_t launch_copy(const LaunchCtx &c);    // copy / compaction
 hipError_t launch_resample(const LaunchCtx &c);
 hipError_t launch_hist_current(const LaunchCtx &c);

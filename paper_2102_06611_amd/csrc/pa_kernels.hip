@@ -2296,6 +2296,236 @@ hipError_t launch_reduce(const LaunchCtx &c) {
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------ runs combined
+// One block per step i: the batch's runs combined at beta_i (the definitions
+// are in include/pa.h, pa_weighted).  The weights are formed in log space
+// relative to their maximum, R_i e^{x - x_max} with x = -beta_i F_i, and the
+// fluctuating-size factor as exp(sum_k ln(R_{k-1} / R)); every sum runs over
+// the runs in a fixed order (deterministic).
+constexpr int kWSums = 17;
+
+template <int K>
+__device__ inline void block_sum_f64v(double (&v)[K], double *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_f64(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) sh[wave * K + k] = v[k];
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += sh[w * K + k];
+        v[k] = t;  // every thread
+    }
+    __syncthreads();
+}
+__device__ inline double block_max_f64(double v, double *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = -INFINITY;
+    for (int w = 0; w < nw; ++w) t = fmax(t, sh[w]);
+    __syncthreads();
+    return t;
+}
+
+__global__ void __launch_bounds__(256) k_weighted(const RunDesc *runs, int n_runs, int first,
+                                                  pa_weighted *out) {
+    __shared__ double sh[4 * kWSums];
+    __shared__ int mixed;
+    const int i = first + (int)blockIdx.x;
+    const double beta = runs[0].records[i].beta;
+    const int N = runs[0].N;
+    if (threadIdx.x == 0) mixed = 0;
+    __syncthreads();
+    // pass 1: log weights (Eq. weighted-averages, and with the size factor
+    // of Eq. modified-weights2) and their maxima
+    double la_max = -INFINITY, lb_max = -INFINITY;
+    for (int m = threadIdx.x; m < n_runs; m += blockDim.x) {
+        const pa_obs &o = runs[m].records[i];
+        if (o.beta != beta) atomicOr(&mixed, 1);
+        const double la = o.minus_beta_F + log((double)o.R_i);
+        double lr = 0.0;
+        for (int k = 1; k <= i; ++k) lr += log((double)runs[m].records[k - 1].R_i / (double)runs[m].R);
+        la_max = fmax(la_max, la);
+        lb_max = fmax(lb_max, la + lr);
+    }
+    la_max = block_max_f64(la_max, sh);
+    lb_max = block_max_f64(lb_max, sh);
+    // pass 2: weighted and plain moment sums, own estimates and beta F
+    double v[kWSums];
+    for (int k = 0; k < kWSums; ++k) v[k] = 0.0;
+    for (int m = threadIdx.x; m < n_runs; m += blockDim.x) {
+        const pa_obs &o = runs[m].records[i];
+        const double R = (double)o.R_i;
+        const double la = o.minus_beta_F + log(R);
+        double lr = 0.0;
+        for (int k = 1; k <= i; ++k) lr += log((double)runs[m].records[k - 1].R_i / (double)runs[m].R);
+        const double a = exp(la - la_max), b = exp(la + lr - lb_max);
+        const double mom[4] = {(double)o.sum_E / R, (double)o.sum_E2 / R, (double)o.sum_absM / R,
+                               (double)o.sum_M2 / R};
+        for (int q = 0; q < 4; ++q) {
+            v[q] += a * mom[q];
+            v[4 + q] += b * mom[q];
+            v[8 + q] += mom[q];
+        }
+        v[12] += a;
+        v[13] += b;
+        v[14] += a * a;
+        v[15] += -o.minus_beta_F;  // beta_i F_i^m
+        v[16] += (double)runs[m].R;
+    }
+    block_sum_f64v(v, sh);
+    const double M = (double)n_runs, Fbar = v[15] / M;
+    // pass 3: spread over the runs (centred sums)
+    double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double obar[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int m = threadIdx.x; m < n_runs; m += blockDim.x) {
+            const pa_obs &o = runs[m].records[i];
+            s4[0] += o.e;
+            s4[1] += o.m;
+            s4[2] += o.c_v;
+            s4[3] += o.chi;
+        }
+        block_sum_f64v(s4, sh);
+        for (int q = 0; q < 4; ++q) obar[q] = s4[q] / M;
+    }
+    for (int m = threadIdx.x; m < n_runs; m += blockDim.x) {
+        const pa_obs &o = runs[m].records[i];
+        const double dF = -o.minus_beta_F - Fbar;
+        c[0] += dF * dF;
+        c[1] += (o.e - obar[0]) * dF;
+        c[2] += (o.m - obar[1]) * dF;
+        c[3] += (o.c_v - obar[2]) * dF;
+        c[4] += (o.chi - obar[3]) * dF;
+    }
+    block_sum_f64v(c, sh);
+    if (threadIdx.x == 0) {
+        double f[20];
+        auto obs = [&](const double *mom, double norm, double *dst) {
+            const double E1 = mom[0] / norm, E2 = mom[1] / norm, A1 = mom[2] / norm, A2 = mom[3] / norm;
+            dst[0] = E1 / N;
+            dst[1] = A1 / N;
+            dst[2] = beta * beta * (E2 - E1 * E1) / N;
+            dst[3] = beta * (A2 - A1 * A1) / N;
+        };
+        obs(v, v[12], f);           // weighted
+        obs(v + 4, v[13], f + 4);   // weighted, fluctuating size
+        obs(v + 8, M, f + 8);       // plain
+        f[12] = 1.0 / v[12];        // the largest weight has a = 1
+        f[13] = v[12] * v[12] / v[14];
+        const double nan = __builtin_nan("");
+        const double var = n_runs > 1 ? c[0] / (M - 1.0) : nan;
+        f[14] = var;
+        f[15] = v[16] / M * var;
+        for (int q = 0; q < 4; ++q) f[16 + q] = n_runs > 1 ? c[1 + q] / (M - 1.0) : nan;
+        if (mixed)
+            for (int q = 0; q < 20; ++q) f[q] = nan;
+        pa_weighted w;
+        w.step = i;
+        w.n_runs = mixed ? 0 : n_runs;
+        w.beta = beta;
+        w.e = f[0]; w.m = f[1]; w.c_v = f[2]; w.chi = f[3];
+        w.e_mod = f[4]; w.m_mod = f[5]; w.c_v_mod = f[6]; w.chi_mod = f[7];
+        w.e_plain = f[8]; w.m_plain = f[9]; w.c_v_plain = f[10]; w.chi_plain = f[11];
+        w.omega_max = f[12];
+        w.n_eff_runs = f[13];
+        w.var_beta_F = f[14];
+        w.rho_f = f[15];
+        w.cov_e = f[16]; w.cov_m = f[17]; w.cov_c_v = f[18]; w.cov_chi = f[19];
+        out[blockIdx.x] = w;
+    }
+}
+
+// ------------------------------------------------------------------ overlap correlation
+// C_q(d) of the current population (Eq. overlap_correlation).  On 1-bit
+// words the sites where replicas i and i + d differ are the set bits of
+// w_g XOR (the partner word), whose lane l holds replica 64 g + l + d: with
+// d = 64 a + b it is (w_{g+a} >> b) | (w_{g+a+1} << (64 - b)).  So
+//   sum_{i < R - d} sum_k s_k^(i) s_k^(i+d) = N (R - d) - 2 H(d),
+// H(d) the popcount of those words over every site and group, lanes with
+// i + d >= R masked off.  A block takes kCqSites sites of kCqGroups groups
+// (its own words and the partner rows, staged in LDS; int8 sites are packed
+// to bits on the way) and 256 distances, one per thread; a wavefront's 64
+// distances share a, so its partner reads are LDS broadcasts.  Each thread
+// adds its integer count to cq[d] as a double (exact: H(d) < 2^53).
+constexpr int kCqSites = 8, kCqGroups = 128, kCqRows = kCqGroups + 5;
+
+__global__ void __launch_bounds__(256) k_cq_zero(double *cq, int n) {
+    const int d = blockIdx.x * 256 + threadIdx.x;
+    if (d < n) cq[d] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_cq(const RunDesc *runs, int d_max, double *cq) {
+    __shared__ uint64_t own[kCqGroups][kCqSites], par[kCqRows][kCqSites];
+    const RunDesc &rd = runs[0];
+    const RunState *st = rd.st;
+    const int R = st->R_cur, N = rd.N, G = (R + 63) >> 6;
+    const int s0 = blockIdx.x * kCqSites, g0 = blockIdx.y * kCqGroups, dc = blockIdx.z;
+    const int a_lo = 4 * dc;  // partner groups of this block's distances: a_lo .. a_lo + 3 (+1)
+    auto word = [&](int g, int site) -> uint64_t {
+        if (g >= G || site >= N) return 0ull;
+        if (rd.layout == PA_LAYOUT_MSC64) return rd.ms[st->cur][(size_t)g * N + site];
+        const uint4 *p = reinterpret_cast<const uint4 *>(rd.s8[st->cur] + ((size_t)g * N + site) * 64);
+        uint64_t w = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w |= (uint64_t)pack16(p[q]) << (16 * q);
+        return w;
+    };
+    for (int e = threadIdx.x; e < kCqGroups * kCqSites; e += blockDim.x) {
+        const int gi = e / kCqSites, si = e - gi * kCqSites;
+        own[gi][si] = word(g0 + gi, s0 + si);
+    }
+    for (int e = threadIdx.x; e < kCqRows * kCqSites; e += blockDim.x) {
+        const int gi = e / kCqSites, si = e - gi * kCqSites;
+        par[gi][si] = word(g0 + a_lo + gi, s0 + si);
+    }
+    __syncthreads();
+    const int d = dc * 256 + (int)threadIdx.x;
+    if (d < 1 || d > d_max) return;
+    const int a = d >> 6, b = d & 63, ar = a - a_lo;  // ar in 0 .. 3
+    const int ng = min(kCqGroups, G - g0), ns = min(kCqSites, N - s0);
+    // lanes of group g whose partner exists: i + d < R, i = 64 g + lane
+    const bool tail = 64 * (g0 + ng) + d > R;
+    uint32_t cnt = 0;
+    for (int si = 0; si < ns; ++si) {
+        for (int gi = 0; gi < ng; ++gi) {
+            const uint64_t lo = par[gi + ar][si], hi = par[gi + ar + 1][si];
+            const uint64_t p = (lo >> b) | ((hi << 1) << (63 - b));
+            uint64_t x = own[gi][si] ^ p;
+            if (tail) x &= lane_mask(R - d - 64 * (g0 + gi));
+            cnt += (uint32_t)__popcll(x);
+        }
+    }
+    atomicAdd(&cq[d], (double)cnt);
+}
+
+__global__ void __launch_bounds__(256) k_cq_finish(const RunDesc *runs, int d_max, double *cq) {
+    const int d = blockIdx.x * 256 + threadIdx.x;
+    if (d > d_max) return;
+    const double R = (double)runs[0].st->R_cur, N = (double)runs[0].N;
+    cq[d] = d == 0 ? 1.0 : 1.0 - 2.0 * cq[d] / (N * (R - d));
+}
+
+hipError_t launch_overlap_correlation(const LaunchCtx &c, int N, int R, int d_max, double *cq) {
+    const int n = d_max + 1, nb = (n + 255) / 256;
+    PA_LAUNCH(k_cq_zero, dim3(nb), dim3(256), 0, c.stream, cq, n);
+    const dim3 grid((N + kCqSites - 1) / kCqSites, ((R + 63) / 64 + kCqGroups - 1) / kCqGroups,
+                    (d_max + 256) / 256);
+    PA_LAUNCH(k_cq, grid, dim3(256), 0, c.stream, c.runs, d_max, cq);
+    PA_LAUNCH(k_cq_finish, dim3(nb), dim3(256), 0, c.stream, c.runs, d_max, cq);
+    return hipSuccess;
+}
+
+hipError_t launch_weighted(const LaunchCtx &c, int first, int count, pa_weighted *out) {
+    PA_LAUNCH(k_weighted, dim3(count), dim3(256), 0, c.stream, c.runs, c.n_runs, first, out);
+    return hipSuccess;
+}
+
 hipError_t launch_counts(const LaunchCtx &c) {
     PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
     if (c.any_nearest)

@@ -37,6 +37,7 @@ def test_struct_layouts_match_header():
     # pa_config: 3 int32 + pointer + 2 int32 + uint64 + 4 int32 (with padding)
     assert ctypes.sizeof(pa.pa_config) == 48
     assert ctypes.sizeof(pa.pa_obs) == 8 + 8 + 4 * 8 + 4 * 8 + 2 * 8 + 3 * 8 + 3 * 8 + 6 * 8
+    assert ctypes.sizeof(pa.pa_weighted) == 8 + 8 + 20 * 8
 
 
 def _cfg(**kw):

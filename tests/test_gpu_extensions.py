@@ -55,6 +55,114 @@ def test_batch_of_uneven_runs_matches_single_runs_and_oracle():
     b.close()
 
 
+def _close_weighted(got, want, ctx):
+    from oracle import weighted as wt
+    assert got["step"] == want["step"] and got["n_runs"] == want["n_runs"], ctx
+    # the device combines the runs in binary64 from its own records, whose
+    # -beta F agree with the oracle's to ~1e-15 relative; covariances are
+    # compared on the scale sqrt(var(O) var(beta F)) of their Cauchy-Schwarz bound
+    for k in wt.FIELDS:
+        a, b = got[k], want[k]
+        if math.isnan(b):
+            assert math.isnan(a), (ctx, k, a, b)
+            continue
+        tol = 1e-8 * max(abs(a), abs(b))
+        if k.startswith("cov_"):
+            tol = max(tol, 1e-8 * math.sqrt(want["var_beta_F"]) * want["_sd_" + k[4:]])
+        assert abs(a - b) <= tol + 1e-300, (ctx, k, a, b)
+
+
+@pytest.mark.parametrize("resample", ["nearest", "poisson", "multinomial"])
+def test_weighted_averages_over_runs_match_oracle(resample):
+    from oracle import weighted as wt
+    L, n, M = 8, 6, 7
+    betas = linear_schedule(0.6, n)
+    Rs = [100, 160, 100, 220, 130, 100, 190]
+    specs = [dict(L=L, R=Rs[m], theta=2, seed=500 + m, resample=resample,
+                  layout="msc64" if m % 2 else "int8", betas=betas) for m in range(M)]
+    b = pa.Batch(specs)
+    b.run(n)
+    got = b.weighted(0, n + 1)
+    refs = [po.run(L, Rs[m], betas, 2, 500 + m, resample) for m in range(M)]
+    for i in range(n + 1):
+        want = wt.weighted_averages(L, [r.records for r in refs], Rs, i)
+        for k in ("e", "m", "c_v", "chi"):
+            want["_sd_" + k] = float(np.std([getattr(r.records[i], k) for r in refs], ddof=1))
+        _close_weighted(got[i], want, "%s step %d" % (resample, i))
+    # one step alone gives the same record
+    assert b.weighted(3)[0] == got[3]
+    b.close()
+
+
+def test_weighted_averages_reject_mixed_runs():
+    specs = [dict(L=8, R=64, theta=1, seed=1, betas=linear_schedule(0.3, 3)),
+             dict(L=8, R=64, theta=1, seed=2, betas=linear_schedule(0.4, 3))]
+    b = pa.Batch(specs)
+    b.run(3)
+    w = b.weighted(0, 4)
+    assert w[0]["n_runs"] == 2  # beta_0 = 0 is shared
+    assert all(x["n_runs"] == 0 and math.isnan(x["e"]) for x in w[1:])
+    with pytest.raises(pa.PAError):
+        b.weighted(3, 2)  # step 4 not reached
+    b.close()
+    b = pa.Batch([dict(L=8, R=64, theta=1, seed=1, betas=linear_schedule(0.3, 2)),
+                  dict(L=6, R=64, theta=1, seed=2, betas=linear_schedule(0.3, 2))])
+    b.run(2)
+    with pytest.raises(pa.PAError) as ei:
+        b.weighted(1)
+    assert ei.value.status == pa.PA_ERR_ARG
+    b.close()
+
+
+def _cq_integer(c, N, R):
+    """The exact integer sum over pairs and sites behind each C_q(d)."""
+    return [int(round(c[d] * N * (R - d))) for d in range(len(c))]
+
+
+@pytest.mark.parametrize("L,R,n,layout", [(8, 300, 10, "msc64"), (8, 300, 10, "int8"),
+                                          (6, 1000, 6, "msc64"), (4, 64, 3, "int8")])
+def test_overlap_correlation_matches_oracle(L, R, n, layout):
+    from oracle import overlap as ov
+    betas = linear_schedule(0.44, n)
+    run = pa.Run(L, R, betas, 1, PARITY_SEED, "nearest", layout)
+    run.run(n)
+    ref = po.run(L, R, betas, 1, PARITY_SEED, "nearest")
+    R_i = len(ref.E)
+    assert run.current() == (n, R_i)
+    d_max = R_i - 1
+    got = run.overlap_correlation(d_max)
+    want = ov.overlap_correlation(ref.spins, d_max)
+    assert _cq_integer(got, L * L, R_i) == _cq_integer(want, L * L, R_i)
+    assert np.allclose(got, want, rtol=0, atol=1e-14)
+    # a shorter range gives the same values
+    assert np.array_equal(run.overlap_correlation(5), got[:6])
+    for bad in (0, R_i):
+        with pytest.raises(pa.PAError):
+            run.overlap_correlation(bad)
+    run.close()
+
+
+@pytest.mark.slow
+def test_overlap_correlation_full_size_sampled():
+    """L=64, R=100000 after 120 of 200 steps to 0.4407: C_q at sampled
+    distances (within a group, across one and several group boundaries, past
+    the first 256-distance chunk) against the plain sum over the downloaded
+    population."""
+    L, R = 64, 100_000
+    run = pa.Run(L, R, linear_schedule(0.4407, 200), 10, PARITY_SEED, "multinomial", "msc64")
+    run.run(120)
+    got = run.overlap_correlation(1100)
+    spins, _, _, _ = run.population()
+    R_i = spins.shape[0]
+    N = L * L
+    for d in (1, 2, 63, 64, 65, 127, 255, 256, 257, 700, 1100):
+        total = N * (R_i - d) - 2 * int(np.count_nonzero(spins[: R_i - d] != spins[d:]))
+        assert _cq_integer(got, N, R_i)[d] == total, d
+    # beta = 0.26 with theta = 10: the population is nearly uncorrelated
+    assert got[0] == 1.0 and np.abs(got[1:]).max() < 0.05
+    run.close()
+
+
 def test_batch_covering_design_runs_and_replays():
     from workloads import batched_design
     specs = []
