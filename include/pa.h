@@ -282,7 +282,8 @@ pa_status pa_overlap_correlation(pa_ctx *ctx, int32_t d_max, double *dev_cq);
  * each run's own e, m, c_v, chi with its beta_i F_i^m (the bias estimate). */
 typedef struct pa_weighted {
     int32_t step;          /* i */
-    int32_t n_runs;        /* M; 0 when the runs do not share beta_i (every field NaN) */
+    int32_t n_runs;        /* M; 0 when the runs do not share beta_i or one stopped (on a
+                              device status) before step i: every field NaN */
     double beta;           /* beta_i */
     double e, m, c_v, chi;                          /* Eq. weighted-averages */
     double e_mod, m_mod, c_v_mod, chi_mod;          /* Eq. modified-weights2 */
@@ -296,8 +297,8 @@ typedef struct pa_weighted {
 
 /* Steps first .. first + count - 1 of all runs of b, one pa_weighted each,
  * into dev_out (device memory, count elements), asynchronously on the
- * batch's stream.  The runs must have one lattice size L and have reached
- * the last step (it waits for the queued steps to check this); PA_ERR_ARG
+ * batch's stream (after the steps queued before it).  The runs must have one
+ * lattice size L and the last step must be queued for every run; PA_ERR_ARG
  * otherwise, or for count < 1 or first < 0. */
 pa_status pa_batch_weighted(pa_batch *b, int32_t first, int32_t count, pa_weighted *dev_out);
 void pa_batch_destroy(pa_batch *b);

@@ -405,7 +405,7 @@ class Batch:
                           device=self.workspace.device)
         _check(lib().pa_batch_weighted(self.h, int(first), int(count),
                                        ctypes.c_void_p(dev.data_ptr())), self.h, batch=True)
-        self.sync()
+        torch.cuda.synchronize(dev.device)  # a run's device status does not stop the read
         host = dev.cpu().numpy().tobytes()
         arr = (pa_weighted * count).from_buffer_copy(host)
         return [{k: getattr(w, k) for k, _ in pa_weighted._fields_} for w in arr]

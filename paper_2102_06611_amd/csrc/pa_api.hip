@@ -1004,13 +1004,7 @@ pa_status pa_batch_weighted(pa_batch *b, int32_t first, int32_t count, pa_weight
     if (last < first) return fail(b, PA_ERR_ARG, "bad arguments");
     for (int r = 0; r < b->n; ++r) {
         if (b->cfg[r].L != b->cfg[0].L) return fail(b, PA_ERR_ARG, "the runs differ in L");
-        RunState s;
-        pa_status e = read_state(b, r, &s);
-        if (e) return e;
-        if (last > s.step) {
-            if (s.err) return fail(b, s.err, "step not reached: a run stopped on a device status");
-            return fail(b, PA_ERR_ARG, "step not reached yet");
-        }
+        if (last > b->host_step[r]) return fail(b, PA_ERR_ARG, "step not queued yet");
     }
     PA_HIP(b, launch_weighted(b->lc, first, count, dev_out));
     return PA_OK;

@@ -2331,26 +2331,52 @@ __device__ inline double block_max_f64(double v, double *sh) {
     return t;
 }
 
+constexpr int kMaxWeightedRuns = 4096;
+
 __global__ void __launch_bounds__(256) k_weighted(const RunDesc *runs, int n_runs, int first,
                                                   pa_weighted *out) {
-    __shared__ double sh[4 * kWSums];
+    __shared__ double sh[4 * kWSums], part[256], lr_sh[kMaxWeightedRuns];
     __shared__ int mixed;
     const int i = first + (int)blockIdx.x;
     const double beta = runs[0].records[i].beta;
     const int N = runs[0].N;
     if (threadIdx.x == 0) mixed = 0;
     __syncthreads();
-    // pass 1: log weights (Eq. weighted-averages, and with the size factor
-    // of Eq. modified-weights2) and their maxima
+    // the size factor of Eq. modified-weights2 in logs, lr_m = sum_{k=1}^{i}
+    // ln(R_{k-1} / R^m): tpr threads per run take every tpr-th k, their
+    // partial sums combined in a fixed order
+    const int tpr = max(1, (int)blockDim.x / n_runs), rpp = (int)blockDim.x / tpr;
+    for (int m0 = 0; m0 < n_runs; m0 += rpp) {
+        const int m = m0 + (int)threadIdx.x / tpr, sub = (int)threadIdx.x % tpr;
+        double s = 0.0;
+        if (m < n_runs && (int)threadIdx.x < rpp * tpr) {
+            const RunDesc &rd = runs[m];
+            for (int k = 1 + sub; k <= i; k += tpr) s += log((double)rd.records[k - 1].R_i / (double)rd.R);
+        }
+        part[threadIdx.x] = s;
+        __syncthreads();
+        if ((int)threadIdx.x < rpp && m0 + (int)threadIdx.x < n_runs) {
+            double t = 0.0;
+            for (int q = 0; q < tpr; ++q) t += part[threadIdx.x * tpr + q];
+            lr_sh[m0 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+    // pass 1: log weights (Eq. weighted-averages, and with the size factor)
+    // and their maxima; a run that stopped before step i, or a different
+    // beta_i, leaves the step uncombined
     double la_max = -INFINITY, lb_max = -INFINITY;
     for (int m = threadIdx.x; m < n_runs; m += blockDim.x) {
+        const RunState *st = runs[m].st;
+        if (st->err != 0 && st->err_step <= i) {
+            atomicOr(&mixed, 1);
+            continue;
+        }
         const pa_obs &o = runs[m].records[i];
         if (o.beta != beta) atomicOr(&mixed, 1);
         const double la = o.minus_beta_F + log((double)o.R_i);
-        double lr = 0.0;
-        for (int k = 1; k <= i; ++k) lr += log((double)runs[m].records[k - 1].R_i / (double)runs[m].R);
         la_max = fmax(la_max, la);
-        lb_max = fmax(lb_max, la + lr);
+        lb_max = fmax(lb_max, la + lr_sh[m]);
     }
     la_max = block_max_f64(la_max, sh);
     lb_max = block_max_f64(lb_max, sh);
@@ -2361,9 +2387,7 @@ __global__ void __launch_bounds__(256) k_weighted(const RunDesc *runs, int n_run
         const pa_obs &o = runs[m].records[i];
         const double R = (double)o.R_i;
         const double la = o.minus_beta_F + log(R);
-        double lr = 0.0;
-        for (int k = 1; k <= i; ++k) lr += log((double)runs[m].records[k - 1].R_i / (double)runs[m].R);
-        const double a = exp(la - la_max), b = exp(la + lr - lb_max);
+        const double a = exp(la - la_max), b = exp(la + lr_sh[m] - lb_max);
         const double mom[4] = {(double)o.sum_E / R, (double)o.sum_E2 / R, (double)o.sum_absM / R,
                                (double)o.sum_M2 / R};
         for (int q = 0; q < 4; ++q) {

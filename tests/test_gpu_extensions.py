@@ -103,7 +103,17 @@ def test_weighted_averages_reject_mixed_runs():
     assert w[0]["n_runs"] == 2  # beta_0 = 0 is shared
     assert all(x["n_runs"] == 0 and math.isnan(x["e"]) for x in w[1:])
     with pytest.raises(pa.PAError):
-        b.weighted(3, 2)  # step 4 not reached
+        b.weighted(3, 2)  # step 4 not queued
+    b.close()
+    # a run that stops (capacity) leaves the later steps uncombined
+    betas = linear_schedule(0.6, 40)
+    b = pa.Batch([dict(L=8, R=128, theta=1, seed=2, betas=betas, capacity=128),
+                  dict(L=8, R=128, theta=1, seed=3, betas=betas)])
+    b.run(40)
+    w = b.weighted(0, 41)
+    stop = next(i for i, x in enumerate(w) if x["n_runs"] == 0)
+    assert stop > 1 and all(x["n_runs"] == 2 for x in w[:stop])
+    assert all(x["n_runs"] == 0 and math.isnan(x["e"]) for x in w[stop:])
     b.close()
     b = pa.Batch([dict(L=8, R=64, theta=1, seed=1, betas=linear_schedule(0.3, 2)),
                   dict(L=6, R=64, theta=1, seed=2, betas=linear_schedule(0.3, 2))])
