@@ -13,6 +13,7 @@
 //   k_reduce       population sums, family statistics, next energy histogram
 //   k_record       record i; the new population becomes current
 #include <climits>
+#include <type_traits>
 
 #include "pa_block.hpp"
 #include "pa_device.hpp"
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     dd w{1.0, 0.0}, stride{1.0, 0.0};
     if (!exact) {
         if (threadIdx.x > 0) dd_exp_neg(dd_mul_d(db, 4.0 * threadIdx.x), &w);
-        dd_exp_neg(dd_mul_d(db, 4.0 * blockDim.x), &stride);
+        if (nlev > (int)blockDim.x) dd_exp_neg(dd_mul_d(db, 4.0 * blockDim.x), &stride);
     }
     for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
         rd.wlev[2 * l] = w.hi;
@@ -2475,8 +2476,8 @@ __global__ void __launch_bounds__(256) k_weighted(const RunDesc *runs, int n_run
 // i + d >= R masked off.  A block takes kCqSites sites of kCqGroups groups
 // (its own words and the partner rows, staged in LDS; int8 sites are packed
 // to bits on the way) and 256 distances, one per thread; a wavefront's 64
-// distances share a, so its partner reads are LDS broadcasts.  Each thread
-// adds its integer count to cq[d] as a double (exact: H(d) < 2^53).
+// distances read two partner rows.  Each thread adds its integer count to
+// cq[d] as a double (exact: H(d) < 2^53).
 constexpr int kCqSites = 8, kCqGroups = 128, kCqRows = kCqGroups + 5;
 
 __global__ void __launch_bounds__(256) k_cq_zero(double *cq, int n) {
@@ -2509,22 +2510,42 @@ __global__ void __launch_bounds__(256) k_cq(const RunDesc *runs, int d_max, doub
         par[gi][si] = word(g0 + a_lo + gi, s0 + si);
     }
     __syncthreads();
-    const int d = dc * 256 + (int)threadIdx.x;
+    // wavefront w takes b in [32 hb, 32 hb + 32), hb = w & 1, for the two
+    // partner offsets a = a_lo + 2 (w >> 1) + (lane >> 5): the funnel shift
+    // of the 128-bit (hi:lo) by b is then two 32-bit align operations on
+    // halves chosen by hb alone (uniform in the wavefront)
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+    const int hb = wv & 1;
+    const int ar = 2 * (wv >> 1) + (lane >> 5), b = 32 * hb + (lane & 31);  // ar in 0 .. 3
+    const int d = 64 * (a_lo + ar) + b;
     if (d < 1 || d > d_max) return;
-    const int a = d >> 6, b = d & 63, ar = a - a_lo;  // ar in 0 .. 3
+    const uint32_t sh = (uint32_t)(lane & 31);
     const int ng = min(kCqGroups, G - g0), ns = min(kCqSites, N - s0);
-    // lanes of group g whose partner exists: i + d < R, i = 64 g + lane
-    const bool tail = 64 * (g0 + ng) + d > R;
-    uint32_t cnt = 0;
-    for (int si = 0; si < ns; ++si) {
-        for (int gi = 0; gi < ng; ++gi) {
-            const uint64_t lo = par[gi + ar][si], hi = par[gi + ar + 1][si];
-            const uint64_t p = (lo >> b) | ((hi << 1) << (63 - b));
-            uint64_t x = own[gi][si] ^ p;
-            if (tail) x &= lane_mask(R - d - 64 * (g0 + gi));
-            cnt += (uint32_t)__popcll(x);
+    // every lane of group g0 + gi has its partner (i + d < R, i = 64 g + lane)
+    // for gi < full; the groups after it are masked
+    const int full = max(0, min(ng, (R - d) / 64 - g0));
+    auto count_pairs = [&](auto upper) -> uint32_t {
+        uint32_t cnt = 0;
+        for (int si = 0; si < ns; ++si) {
+            uint64_t lo = par[ar][si];
+            auto pair = [&](int gi) -> uint64_t {
+                const uint64_t hi = par[gi + ar + 1][si];
+                const uint32_t x0 = (uint32_t)lo, x1 = (uint32_t)(lo >> 32), x2 = (uint32_t)hi,
+                               x3 = (uint32_t)(hi >> 32);
+                const uint32_t p0 = upper ? __builtin_amdgcn_alignbit(x2, x1, sh)
+                                          : __builtin_amdgcn_alignbit(x1, x0, sh);
+                const uint32_t p1 = upper ? __builtin_amdgcn_alignbit(x3, x2, sh)
+                                          : __builtin_amdgcn_alignbit(x2, x1, sh);
+                lo = hi;
+                return own[gi][si] ^ (((uint64_t)p1 << 32) | p0);
+            };
+            int gi = 0;
+            for (; gi < full; ++gi) cnt += (uint32_t)__popcll(pair(gi));
+            for (; gi < ng; ++gi) cnt += (uint32_t)__popcll(pair(gi) & lane_mask(R - d - 64 * (g0 + gi)));
         }
-    }
+        return cnt;
+    };
+    const uint32_t cnt = hb ? count_pairs(std::true_type{}) : count_pairs(std::false_type{});
     atomicAdd(&cq[d], (double)cnt);
 }
 
