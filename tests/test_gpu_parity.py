@@ -386,13 +386,13 @@ def test_l64_multinomial_sampled_step_parity(layout):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("L,k", [(64, 120), (128, 180)])
-def test_heatbath_sampled_step_parity(L, k):
+@pytest.mark.parametrize("L,k,layout", [(64, 120, "msc64"), (128, 180, "msc64"), (128, 180, "int8")])
+def test_heatbath_sampled_step_parity(L, k, layout):
     """Heatbath at full size: L=64 (one group per block, one word per thread)
-    and L=128 (two words per thread), R=100000, nearest."""
-    log("heatbath sampled", L)
+    and L=128 (two words per thread, both layouts), R=100000, nearest."""
+    log("heatbath sampled", L, layout)
     n, bf = (200, 0.4407) if L == 64 else (400, 1.0)
-    _sampled_step_parity(L, 100_000, "nearest", "msc64", n, bf, k, 10, PARITY_SEED, 3,
+    _sampled_step_parity(L, 100_000, "nearest", layout, n, bf, k, 10, PARITY_SEED, 3,
                          update="heatbath")
 
 
