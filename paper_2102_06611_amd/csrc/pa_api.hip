@@ -833,9 +833,16 @@ pa_status pa_profile(pa_ctx *ctx, int32_t enable) {
     if (enable & ~3) return fail(B, PA_ERR_ARG, "enable must be a combination of 1 and 2");
     B->profiling = enable != 0;
     if (B->profiling) B->profiled_steps = 0;
+    if (B->lc.count_calls != ((enable & 2) != 0)) {
+        B->lc.count_calls = (enable & 2) != 0;  // another sweep kernel: drop the captured graph
+        if (B->exec) {
+            (void)hipGraphExecDestroy(B->exec);
+            (void)hipGraphDestroy(B->graph);
+            B->exec = nullptr;
+            B->graph = nullptr;
+        }
+    }
     for (int r = 0; r < B->n; ++r) {
-        const int32_t on = (enable & 2) ? 1 : 0;
-        PA_HIP(B, hipMemcpy(&B->desc[r].st->count_calls, &on, sizeof on, hipMemcpyHostToDevice));
         if (!B->profiling) continue;
         unsigned long long zero[2] = {0, 0};
         PA_HIP(B, hipMemcpy(&B->desc[r].st->philox_calls, zero, sizeof zero, hipMemcpyHostToDevice));

@@ -52,7 +52,7 @@ struct RunState {
     int32_t r_parents;           // R_{i-1} of the last resampling (parents of cnt[])
     int32_t accepted;            // learned proposal passed the overlap guard
     float mlp_y;                 // last MLP output of the learned step
-    int32_t count_calls;         // profiling: the sweeps count the Philox calls the words need
+    int32_t reserved;            // 0
     unsigned long long philox_calls;  // Philox calls counted by the sweeps (profiling)
     unsigned long long sweep_words;   // 64-replica words updated by the sweeps
 };

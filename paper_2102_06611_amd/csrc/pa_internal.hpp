@@ -35,6 +35,7 @@ struct LaunchCtx {
     bool any_nearest, any_multi, any_poisson;
     bool any_msc, any_int8;  // layouts present in the batch
     bool any_update[2];      // spin-update rules present in the batch (PA_UPDATE_*)
+    bool count_calls = false;  // sweeps count the Philox calls the words need (pa_profile 3)
 };
 
 hipError_t configure_kernels();

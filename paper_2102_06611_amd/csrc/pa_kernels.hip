@@ -1609,7 +1609,7 @@ __device__ __forceinline__ uint64_t update_word(uint64_t s0, uint64_t n0, uint64
                            h, count, calls, wcalls);
 }
 
-template <int LAYOUT, int WALK, int ILP, int UPD>
+template <int LAYOUT, int WALK, int ILP, int UPD, int COUNT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ILP == 1 ? 8 : 4)))
 k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     extern __shared__ uint64_t lat[];
@@ -1682,7 +1682,7 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     const uint64_t last_valid = lane_mask(Rn - (g0 + ng - 1) * kLanes);
     const int P = hl.P;
     const uint32_t k0 = rd.key0, k1 = rd.key1;
-    const bool count = __builtin_amdgcn_readfirstlane(st->count_calls) != 0;  // uniform
+    constexpr bool count = COUNT != 0;  // profiling builds of the kernel count Philox calls
     // kWalkOneGroup: the thread's column xh1, first row y1 and row stride dy1
     const int y1 = tid / half, xh1 = tid - y1 * half, dy1 = nt / half, dsite1 = dy1 * P;
     uint32_t calls = 0, wcalls = 0;
@@ -2252,22 +2252,25 @@ hipError_t launch_init(const LaunchCtx &c) {
 size_t sweep_lds_bytes(int L, int gpb) { return (size_t)gpb * (L + 2) * (L + 2) * 8; }
 
 // k_sweep instantiation for a layout, a word walk and words per thread at once
-template <int UPD>
+template <int UPD, int C>
 static const void *sweep_kernel_of(int layout, int walk, int ilp) {
     static const void *const fns[2][3][2] = {
-        {{(const void *)k_sweep<0, kWalkAny, 1, UPD>, (const void *)k_sweep<0, kWalkAny, 2, UPD>},
-         {(const void *)k_sweep<0, kWalkRows, 1, UPD>, (const void *)k_sweep<0, kWalkRows, 2, UPD>},
-         {(const void *)k_sweep<0, kWalkOneGroup, 1, UPD>,
-          (const void *)k_sweep<0, kWalkOneGroup, 2, UPD>}},
-        {{(const void *)k_sweep<1, kWalkAny, 1, UPD>, (const void *)k_sweep<1, kWalkAny, 2, UPD>},
-         {(const void *)k_sweep<1, kWalkRows, 1, UPD>, (const void *)k_sweep<1, kWalkRows, 2, UPD>},
-         {(const void *)k_sweep<1, kWalkOneGroup, 1, UPD>,
-          (const void *)k_sweep<1, kWalkOneGroup, 2, UPD>}}};
+        {{(const void *)k_sweep<0, kWalkAny, 1, UPD, C>, (const void *)k_sweep<0, kWalkAny, 2, UPD, C>},
+         {(const void *)k_sweep<0, kWalkRows, 1, UPD, C>, (const void *)k_sweep<0, kWalkRows, 2, UPD, C>},
+         {(const void *)k_sweep<0, kWalkOneGroup, 1, UPD, C>,
+          (const void *)k_sweep<0, kWalkOneGroup, 2, UPD, C>}},
+        {{(const void *)k_sweep<1, kWalkAny, 1, UPD, C>, (const void *)k_sweep<1, kWalkAny, 2, UPD, C>},
+         {(const void *)k_sweep<1, kWalkRows, 1, UPD, C>, (const void *)k_sweep<1, kWalkRows, 2, UPD, C>},
+         {(const void *)k_sweep<1, kWalkOneGroup, 1, UPD, C>,
+          (const void *)k_sweep<1, kWalkOneGroup, 2, UPD, C>}}};
     return fns[layout][walk][ilp - 1];
 }
-static const void *sweep_kernel(int layout, int walk, int ilp, int upd) {
-    return upd == PA_UPDATE_HEATBATH ? sweep_kernel_of<PA_UPDATE_HEATBATH>(layout, walk, ilp)
-                                     : sweep_kernel_of<PA_UPDATE_METROPOLIS>(layout, walk, ilp);
+static const void *sweep_kernel(int layout, int walk, int ilp, int upd, bool count) {
+    if (upd == PA_UPDATE_HEATBATH)
+        return count ? sweep_kernel_of<PA_UPDATE_HEATBATH, 1>(layout, walk, ilp)
+                     : sweep_kernel_of<PA_UPDATE_HEATBATH, 0>(layout, walk, ilp);
+    return count ? sweep_kernel_of<PA_UPDATE_METROPOLIS, 1>(layout, walk, ilp)
+                 : sweep_kernel_of<PA_UPDATE_METROPOLIS, 0>(layout, walk, ilp);
 }
 
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
@@ -2281,7 +2284,7 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init) {
             if (!(layout == PA_LAYOUT_MSC64 ? cls.has_msc : cls.has_int8)) continue;
             for (int upd = 0; upd < 2; ++upd) {
                 if (!c.any_update[upd]) continue;
-                const void *fn = sweep_kernel(layout, walk, ilp, upd);
+                const void *fn = sweep_kernel(layout, walk, ilp, upd, c.count_calls);
                 void *args[] = {(void *)&c.runs, (void *)&cls.map, (void *)&init, (void *)&cls.gpb};
                 hipError_t e = hipLaunchKernel(fn, dim3(cls.total), dim3(cls.threads), args, lds, c.stream);
                 if (e != hipSuccess) return e;
@@ -2672,8 +2675,8 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 
 hipError_t configure_kernels() {
     // up to kMaxSweepLds bytes of lattices (with their halo) per sweep block
-    for (int k = 0; k < 24; ++k) {
-        const void *f = sweep_kernel((k / 6) & 1, (k / 2) % 3, k % 2 + 1, k / 12);
+    for (int k = 0; k < 48; ++k) {
+        const void *f = sweep_kernel((k / 6) & 1, (k / 2) % 3, k % 2 + 1, (k / 12) & 1, k >= 24);
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
         if (e != hipSuccess) return e;
     }
