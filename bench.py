@@ -230,7 +230,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs one population per device and "
+        print("bench.py measures one GPU: the library runs each population on one device and "
               "uses no collectives; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     K = max(1, min(args.steps, N_STEPS))

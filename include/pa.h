@@ -314,7 +314,8 @@ pa_status pa_philox4x32_10(uint32_t key0, uint32_t key1, const uint32_t *dev_ctr
 /* ---- learned temperature steps --------------------------------------------
  * A multilayer perceptron 35 -> 64 -> 64 -> 1 (tanh hidden layers, FP32)
  * proposes the next dbeta from the energy histogram of the population; the
- * histogram-overlap criterion (pa_overlap) is the fallback and the judge.
+ * histogram-overlap criterion (pa_overlap) is the fallback and decides
+ * whether a proposal is taken.
  * Parameters live in one caller-owned device array of PA_MLP_PARAMS floats:
  * W1[64][35], b1[64], W2[64][64], b2[64], w3[64], b3. */
 #define PA_MLP_IN 35

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.  Plain numpy in double precision; the device
 kernels compute in FP32.  The learned part is not in the paper: the network
 proposes the next inverse-temperature step from the population's energy
 histogram; the histogram-overlap criterion of the self-adaptive schedule
-(Sec. "Algorithm") stays the fallback and judge.
+(Sec. "Algorithm") stays the fallback and decides whether a proposal is taken.
 
 Parameters (one flat vector): W1[64][35], b1[64], W2[64][64], b2[64], w3[64], b3.
 Network: h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = w3 . h2 + b3.
