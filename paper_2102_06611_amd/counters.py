@@ -7,7 +7,7 @@ calibrated HBM bytes of a kernel are its FETCH_SIZE times (1 GiB / the copy's
 FETCH_SIZE) plus its WRITE_SIZE times (1 GiB / the copy's WRITE_SIZE).
 
     python -m paper_2102_06611_amd.counters --kernel k_sweep_msc64 \\
-        --match 'k_sweep<1, 2, 1, 0>' --fetch F.csv --write W.csv \\
+        --match 'k_sweep<1, 2, 1, 0, 0>' --fetch F.csv --write W.csv \\
         --copy-fetch CF.csv --copy-write CW.csv [--command '...'] [--out profiles/traffic.json]
 
 writes (or updates) the kernel's entry in the JSON file, keyed by a hash of
