@@ -207,10 +207,11 @@ pa_status pa_adaptive_dbeta(pa_ctx *ctx, double alpha_target, double dbeta_max, 
  * events on the run's stream before the resampling (histogram, Q_i, copy
  * counts, offsets, copy/compaction), before the sweeps, before the
  * measurement/record kernel and after it; with the value 2 set in enable
- * the sweep kernel also counts the Philox4x32-10 calls its words need and the
- * words it updates (this costs the sweeps a few per cent: time with
- * enable = 1, count with enable = 3).  A nonzero enable resets the totals;
- * any other bit set: PA_ERR_ARG.  Asynchronous. */
+ * the sweeps run a counting build of the sweep kernel, which also counts the
+ * Philox4x32-10 calls its words need and the words it updates (about 3 %
+ * slower: time with enable = 1, count with enable = 3; changing the value 2
+ * drops a captured step graph).  A nonzero enable resets the totals; any
+ * other bit set: PA_ERR_ARG.  Synchronises. */
 pa_status pa_profile(pa_ctx *ctx, int32_t enable);
 
 /* Totals since profiling was enabled: steps timed, summed milliseconds of the
