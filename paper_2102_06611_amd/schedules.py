@@ -44,8 +44,9 @@ def _step_until_done(run: Run, enqueue, chunk: int = 32) -> int:
 
 def adaptive_run(L: int, R: int, theta: int, seed: int, alpha: float, beta_final: float,
                  max_steps: int = 4000, resample: str = "nearest", layout: str = "msc64",
-                 stream=None) -> Run:
-    run = Run(L, R, None, theta, seed, resample, layout, n_steps=max_steps, stream=stream)
+                 stream=None, update: str = "metropolis") -> Run:
+    run = Run(L, R, None, theta, seed, resample, layout, n_steps=max_steps, stream=stream,
+              update=update)
     _step_until_done(run, lambda: run.anneal_step_adaptive(alpha, beta_final))
     return run
 

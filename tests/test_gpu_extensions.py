@@ -224,14 +224,16 @@ def test_adaptive_dbeta_hits_the_target_overlap():
     run.close()
 
 
-def test_adaptive_schedule_replays_in_the_oracle():
+@pytest.mark.parametrize("update,resample", [("metropolis", "nearest"), ("heatbath", "poisson")])
+def test_adaptive_schedule_replays_in_the_oracle(update, resample):
     L, R, theta = 8, 400, 2
-    run = schedules.adaptive_run(L, R, theta, 41, 0.85, 0.6, max_steps=300)
+    run = schedules.adaptive_run(L, R, theta, 41, 0.85, 0.6, max_steps=300, resample=resample,
+                                 update=update)
     n, acc, alpha = run.schedule_log()
     assert n > 3 and run.observables(n)["beta"] == 0.6
     assert np.all(alpha >= 0.85 - 1e-9) and not acc.any()
     betas = [run.observables(i)["beta"] for i in range(n + 1)]
-    ref = po.OracleRun(L, R, theta, 41, "nearest", np.array(betas))
+    ref = po.OracleRun(L, R, theta, 41, resample, np.array(betas), update=update)
     for i in range(1, n + 1):
         # the step the device chose has the target overlap in the oracle too
         if i < n:
