@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap 
 // then over the at most 64 parents of the chosen stretch.  Four blocks share
 // each slot block's 1024 draws (one draw per thread).
 constexpr int kCoarse = 4096;
-constexpr int kDrawSplit = kSlotBlock / 256;
+constexpr int kDrawSplit = kSlotBlock / 256;  // one draw per thread (two or four were slower)
 
 __global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap map) {
     int b;
@@ -788,9 +788,10 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 }
 
 constexpr int kGatherPass = 256;  // multispin: sites of one wavefront pass (four per lane)
-constexpr int kGatherPasses = 4;  // multispin: passes whose loads are in flight together
+constexpr int kGatherPasses = 2;  // multispin: passes whose loads are in flight together
+constexpr int kGatherThreads = 512;  // multispin: eight wavefronts, one 512-site chunk each at L = 64
 
-__global__ void __launch_bounds__(256) k_gather_msc64(const RunDesc *runs, WorkMap map) {
+__global__ void __launch_bounds__(kGatherThreads) k_gather_msc64(const RunDesc *runs, WorkMap map) {
     GatherJob jb;
     if (!gather_start(runs, map, PA_LAYOUT_MSC64, &jb)) return;
     const RunDesc &rd = *jb.rd;
@@ -2597,7 +2598,8 @@ hipError_t launch_counts(const LaunchCtx &c) {
 
 hipError_t launch_copy(const LaunchCtx &c) {
     if (c.any_msc)
-        PA_LAUNCH(k_gather_msc64, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
+        PA_LAUNCH(k_gather_msc64, dim3(c.groups.total), dim3(kGatherThreads), 0, c.stream, c.runs,
+                  c.groups.map);
     if (c.any_int8)
         PA_LAUNCH(k_gather_int8, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
     return hipSuccess;
