@@ -739,7 +739,10 @@ __device__ __forceinline__ uint64_t net_expand(uint64_t x, const Network &n) {
 //  - int8: the parents' rows of kGatherSites sites at a time are staged in LDS
 //    (16-byte loads); thread = one dword (four children) of every 16th row.
 constexpr int kGatherPg = 4;      // int8: parent groups staged per pass
-constexpr int kGatherSites = 64;  // int8: site rows per pass
+constexpr int kGatherSites = 256;  // int8: site rows per pass (64 and 128 were slower)
+constexpr int kGather8Threads = 4 * kGatherSites;  // int8: one 16-byte stage element per thread
+constexpr int kGather8Step = kGather8Threads / 16;   // int8: site rows a pass step covers
+constexpr int kGather8Out = kGatherSites / kGather8Step;  // int8: output dwords per thread and pass
 
 // Shared start of both gathers: the destination group of the block, the
 // parent of each lane's child and the family labels; false if there is no
@@ -858,7 +861,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_msc64(const RunDesc *
     }
 }
 
-__global__ void __launch_bounds__(256) k_gather_int8(const RunDesc *runs, WorkMap map) {
+__global__ void __launch_bounds__(kGather8Threads) k_gather_int8(const RunDesc *runs, WorkMap map) {
     __shared__ u32x4 stage[kGatherPg * kGatherSites * 4];  // groups x rows x 64 bytes
     GatherJob jb;
     if (!gather_start(runs, map, PA_LAYOUT_INT8, &jb)) return;
@@ -866,7 +869,7 @@ __global__ void __launch_bounds__(256) k_gather_int8(const RunDesc *runs, WorkMa
     const int N = jb.N, p = jb.p, g_first = jb.g_first, g_last = jb.g_last;
     const int cur = jb.cur, nb = jb.nb, gd = jb.gd;
     {
-        // thread -> dword k (children 4k .. 4k + 3) of site rows sl, sl + 16, ...
+        // thread -> dword k (children 4k .. 4k + 3) of site rows sl, sl + kGather8Step, ...
         // of a chunk of kGatherSites rows
         const gptr<const u32x4> src = global(reinterpret_cast<const u32x4 *>(rd.s8[cur]));
         const gptr<uint32_t> dst = global(reinterpret_cast<uint32_t *>(rd.s8[nb] + (size_t)gd * N * kLanes));
@@ -897,9 +900,9 @@ __global__ void __launch_bounds__(256) k_gather_int8(const RunDesc *runs, WorkMa
                     if (b < ngb) stage[b * kPass + threadIdx.x] = pre[b];
                 __syncthreads();
                 if (s0 + kGatherSites < N) load(s0 + kGatherSites);
-                uint32_t out[kGatherSites / 16];
+                uint32_t out[kGather8Out];
 #pragma unroll
-                for (int r = 0; r < kGatherSites / 16; ++r) {
+                for (int r = 0; r < kGather8Out; ++r) {
                     out[r] = 0;
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
@@ -908,22 +911,22 @@ __global__ void __launch_bounds__(256) k_gather_int8(const RunDesc *runs, WorkMa
                         } else {
                             const uint8_t *row = st8 + ((pc[m] >> 6) - g_first) * (kGatherSites * 64) +
                                                  (pc[m] & 63);
-                            out[r] |= (uint32_t)row[(sl + 16 * r) * 64] << (8 * m);
+                            out[r] |= (uint32_t)row[(sl + kGather8Step * r) * 64] << (8 * m);
                         }
                     }
                 }
 #pragma unroll
-                for (int r = 0; r < kGatherSites / 16; ++r) {
-                    const int site = s0 + sl + 16 * r;
+                for (int r = 0; r < kGather8Out; ++r) {
+                    const int site = s0 + sl + kGather8Step * r;
                     if (site < N) dst[(size_t)site * 16 + k] = out[r];
                 }
             }
             return;
         }
         for (int s0 = 0; s0 < N; s0 += kGatherSites) {
-            uint32_t out[kGatherSites / 16];
+            uint32_t out[kGather8Out];
 #pragma unroll
-            for (int r = 0; r < kGatherSites / 16; ++r) {
+            for (int r = 0; r < kGather8Out; ++r) {
                 out[r] = 0;
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
@@ -945,14 +948,14 @@ __global__ void __launch_bounds__(256) k_gather_int8(const RunDesc *runs, WorkMa
                     if (pc[m] >= 0 && rel >= 0 && rel < ngb) {
                         const uint8_t *row = st8 + rel * (kGatherSites * 64) + (pc[m] & 63);
 #pragma unroll
-                        for (int r = 0; r < kGatherSites / 16; ++r)
-                            out[r] |= (uint32_t)row[(sl + 16 * r) * 64] << (8 * m);
+                        for (int r = 0; r < kGather8Out; ++r)
+                            out[r] |= (uint32_t)row[(sl + kGather8Step * r) * 64] << (8 * m);
                     }
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kGatherSites / 16; ++r) {
-                const int site = s0 + sl + 16 * r;
+            for (int r = 0; r < kGather8Out; ++r) {
+                const int site = s0 + sl + kGather8Step * r;
                 if (site < N) dst[(size_t)site * 16 + k] = out[r];
             }
         }
@@ -2601,7 +2604,8 @@ hipError_t launch_copy(const LaunchCtx &c) {
         PA_LAUNCH(k_gather_msc64, dim3(c.groups.total), dim3(kGatherThreads), 0, c.stream, c.runs,
                   c.groups.map);
     if (c.any_int8)
-        PA_LAUNCH(k_gather_int8, dim3(c.groups.total), dim3(256), 0, c.stream, c.runs, c.groups.map);
+        PA_LAUNCH(k_gather_int8, dim3(c.groups.total), dim3(kGather8Threads), 0, c.stream, c.runs,
+                  c.groups.map);
     return hipSuccess;
 }
 
