@@ -294,6 +294,33 @@ def test_update_rules_differ_and_snapshots_keep_the_rule():
     b.close()
 
 
+@pytest.mark.slow
+def test_poisson_mean_limit():
+    """beta 0 -> 50 in one step at L=6, R=100000 with theta = 0: nearly all the
+    weight sits on the lowest occupied level.  Seed 4 has one replica there,
+    so tau_hat ~ 1e5 exceeds the supported 65536 and the step stops with
+    PA_ERR_NUMERIC; seed 1 has four (tau_hat ~ 25000) and its copy counts match
+    the oracle's."""
+    L, R, betas = 6, 100_000, [0.0, 50.0]
+    run = pa.Run(L, R, betas, 0, 4, "poisson", "msc64")
+    run.anneal_step()
+    with pytest.raises(pa.PAError) as ei:
+        run.sync()
+    assert ei.value.status == pa.PA_ERR_NUMERIC
+    assert run.current() == (0, R)
+    run.close()
+    run = pa.Run(L, R, betas, 0, 1, "poisson", "msc64")
+    run.anneal_step()
+    run.sync()
+    ref = po.OracleRun(L, R, 0, 1, "poisson", betas)
+    ref.anneal_step()
+    counts = run.copy_counts()
+    assert np.array_equal(counts, ref.last_counts)
+    assert counts.max() > 10000
+    check_record(run.observables(1), ref.records[1], "seed 1")
+    run.close()
+
+
 def test_extinct_population_is_reported():
     # R = 2, Poisson: for some seeds both parents draw zero copies at step 1
     # (seeds 27 and 35 among 20..39); the device reports PA_ERR_EXTINCT
