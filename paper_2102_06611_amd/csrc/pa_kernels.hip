@@ -424,6 +424,29 @@ __device__ inline int poisson_invert(dd lam, dd G, int e, uint64_t U, bool *amb)
     return kPoissonMax;
 }
 
+// The same inversion in binary64 first.  For lambda <= kPoissonFastMean and
+// k <= kPoissonFastMax the computed 2^64 F(k) has a relative error below
+// (lambda + 4k + 10) 2^-53 < 2^-39 (lambda's own rounding and e^-lambda, two
+// roundings per step of the term recursion, one per addition of the sum),
+// i.e. below 2^25 in units of U, and U converts to binary64 within 2^11; a
+// comparison is taken only with a gap above 2^36.  Returns -1 when it cannot
+// decide (then the double-double inversion runs).
+constexpr double kPoissonFastMean = 600.0;
+constexpr int kPoissonFastMax = 2000;
+__device__ inline int poisson_invert_fast(double lam, uint64_t U) {
+    if (!(lam <= kPoissonFastMean)) return -1;
+    const double Ud = (double)U, gap_min = 0x1p36;
+    double term = exp(-lam), F = term;
+    for (int k = 0; k < kPoissonFastMax; ++k) {
+        const double gap = ldexp(F, 64) - Ud;
+        if (gap > gap_min) return k;  // U < 2^64 F(k)
+        if (gap > -gap_min) return -1;
+        term = term * lam / (double)(k + 1);
+        F += term;
+    }
+    return -1;
+}
+
 __global__ void __launch_bounds__(256) k_counts_poisson(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
@@ -446,7 +469,8 @@ __global__ void __launch_bounds__(256) k_counts_poisson(const RunDesc *runs, Wor
             const int jj = j + m;
             if (jj < Rp) {
                 const double *p = rd.plev + 6 * (((rd.E[jj] + 2 * rd.N) >> 2) - kmin);
-                const int c = poisson_invert(dd{p[0], p[1]}, dd{p[2], p[3]}, (int)p[4], U[m], &amb);
+                int c = poisson_invert_fast(p[0] + p[1], U[m]);
+                if (c < 0) c = poisson_invert(dd{p[0], p[1]}, dd{p[2], p[3]}, (int)p[4], U[m], &amb);
                 rd.cnt[jj] = c;
                 s += c;
                 s2 += (int64_t)c * c;
