@@ -193,7 +193,27 @@ def cpu_baseline(betas, energies):
             "sample": "%d sweeps of 64 replicas (L=64) at beta=%.4f (%.1f s) and one multinomial "
                       "resampling of %d parents (%.2f s), scaled to a step of R=%d, theta=%d"
                       % (sweeps, beta, t_sweep, len(energies), t_res, R, THETA),
-            "step_seconds": step_s, "resample_s_per_step": t_res, "sweep_seconds": t_sweep}
+            "step_seconds": step_s, "resample_s_per_step": t_res, "sweep_seconds": t_sweep,
+            "host": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use; the oracle
+    stays single-threaded, and value x cores is the host's ideal aggregate
+    (context only)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def copy_calibration():
@@ -389,6 +409,8 @@ def main():
     if not args.no_cpu_baseline and energies_mid is not None:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(betas, energies_mid)
+        out["cpu_baseline"]["host"]["ideal_aggregate_attempts_per_ns"] = (
+            out["cpu_baseline"]["value"] * out["cpu_baseline"]["host"]["usable_cpus"])
     print(json.dumps(out))
 
 
