@@ -8,6 +8,10 @@ each pins the others:
 * ``dos_enumeration(L)``: brute force over all 2^(L^2) states (L = 4).
 * ``dos_transfer(L)``: the row-to-row transfer matrix with exact integer
   polynomial entries, giving the integer density of states g(E).
+* ``joint_dos_enumeration(L)`` / ``joint_dos_transfer(L)``: the joint density
+  of states g(E, M) by brute force (L = 4) and by a transfer matrix that also
+  carries the magnetisation, giving the exact <|M|> and <M^2> behind the
+  magnetisation m and the susceptibility chi of Sec. "Model and observables".
 * ``ln_z_kaufman(L, beta)``: Kaufman's closed form for the torus,
   Z = 1/2 (2 sinh 2K)^(N/2) [P1 + P2 + P3 + P4], with
   P1 = prod_r 2 cosh(L g_{2r+1}/2), P2 = prod_r 2 sinh(L g_{2r+1}/2),
@@ -19,7 +23,7 @@ E here is H = -sum_<ij> s_i s_j, so E ranges over [-2N, 2N] in steps of 4.
 """
 from __future__ import annotations
 
-from typing import Dict
+from typing import Dict, Tuple
 
 import mpmath
 import numpy as np
@@ -119,3 +123,75 @@ def energy_distribution(g: Dict[int, int], beta) -> Dict[int, float]:
     w = {e: c * mpmath.exp(-beta * e) for e, c in g.items()}
     z = mpmath.fsum(w.values())
     return {e: float(v / z) for e, v in w.items()}
+
+
+# ---------------------------------------------------------------- magnetisation
+
+def joint_dos_enumeration(L: int) -> Dict[Tuple[int, int], int]:
+    """g(E, M), M = sum of the spins, by visiting every configuration (L <= 4)."""
+    N = L * L
+    assert N <= 20
+    states = np.arange(2 ** N, dtype=np.int64)
+    bits = ((states[:, None] >> np.arange(N, dtype=np.int64)[None, :]) & 1).astype(np.int8)
+    s = (2 * bits - 1).reshape(-1, L, L)
+    E = -(s * np.roll(s, -1, axis=2)).sum(axis=(1, 2)) - (s * np.roll(s, -1, axis=1)).sum(axis=(1, 2))
+    M = s.sum(axis=(1, 2))
+    key = (E.astype(np.int64) + 2 * N) * (2 * N + 1) + (M.astype(np.int64) + N)
+    vals, counts = np.unique(key, return_counts=True)
+    return {(int(v // (2 * N + 1)) - 2 * N, int(v % (2 * N + 1)) - N): int(c)
+            for v, c in zip(vals, counts)}
+
+
+def joint_dos_transfer(L: int) -> Dict[Tuple[int, int], int]:
+    """g(E, M) from a row-to-row transfer matrix whose entries count states by
+    (energy, magnetisation): the row magnetisation is added with each row, the
+    bond energies as in dos_transfer."""
+    nstate = 2 ** L
+    rows = ((np.arange(nstate)[:, None] >> np.arange(L)[None, :]) & 1) * 2 - 1
+    e_in = -(rows * np.roll(rows, -1, axis=1)).sum(axis=1)
+    e_vert = -(rows[:, None, :] * rows[None, :, :]).sum(axis=2)
+    m_row = rows.sum(axis=1)
+    total: Dict[Tuple[int, int], int] = {}
+    for a0 in range(nstate):
+        # dist[b] = {(E, M): ways} over the rows placed so far, last row state b
+        dist = [dict() for _ in range(nstate)]
+        dist[a0][(int(e_in[a0]), int(m_row[a0]))] = 1
+        for _ in range(L - 1):
+            new = [dict() for _ in range(nstate)]
+            for a in range(nstate):
+                if not dist[a]:
+                    continue
+                for b in range(nstate):
+                    de, dm = int(e_vert[a, b] + e_in[b]), int(m_row[b])
+                    tgt = new[b]
+                    for (e, m), c in dist[a].items():
+                        k = (e + de, m + dm)
+                        tgt[k] = tgt.get(k, 0) + c
+            dist = new
+        for a in range(nstate):
+            de = int(e_vert[a, a0])
+            for (e, m), c in dist[a].items():
+                k = (e + de, m)
+                total[k] = total.get(k, 0) + c
+    return total
+
+
+def magnetisation_moments(g2: Dict[Tuple[int, int], int], beta):
+    """(<|M|>, <M^2>) at inverse temperature beta from the joint density of states."""
+    b = mpmath.mpf(beta)
+    w = {k: c * mpmath.exp(-b * k[0]) for k, c in g2.items()}
+    z = mpmath.fsum(w.values())
+    abs_m = mpmath.fsum(abs(k[1]) * v for k, v in w.items()) / z
+    m2 = mpmath.fsum(k[1] * k[1] * v for k, v in w.items()) / z
+    return abs_m, m2
+
+
+def magnetisation_per_spin(L: int, g2, beta) -> mpmath.mpf:
+    """m = <|M|> / N (the finite-lattice order parameter of Sec. "Model and observables")."""
+    return magnetisation_moments(g2, beta)[0] / (L * L)
+
+
+def susceptibility(L: int, g2, beta) -> mpmath.mpf:
+    """chi = beta N (<m^2> - <|m|>^2) = beta (<M^2> - <|M|>^2) / N, m = M / N."""
+    abs_m, m2 = magnetisation_moments(g2, beta)
+    return mpmath.mpf(beta) * (m2 - abs_m * abs_m) / (L * L)
