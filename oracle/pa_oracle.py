@@ -40,6 +40,11 @@ file takes the per-step decisions, following Sec. "Algorithm" steps 1-5:
 * Sec. "Effective population size" and Sec. "Statistical errors": blocking
   R_eff(E), R_eff(|M|) and single-run error bars of e, m, C_V, chi over the
   tree-ordered population (oracle/blocking.py).
+* Sec. "Conclusions" (last guideline) with Eqs. (free-emergy-estimator,
+  jackknife-variance, bias_covariance): the single-run jackknife of -beta F,
+  each sample leaving one block of every parent population out of every Q
+  (oracle/blocking.py gives the reading), and the covariances of e, m, C_V,
+  chi with beta F.
 
 Every integer decision is taken on a 256-bit value and is checked to be at
 least 2^-100 away from its rounding boundary unless the value is exact.
@@ -327,6 +332,11 @@ class Record:
     err_m: float
     err_c_v: float
     err_chi: float
+    jk_var_beta_F: float
+    jk_cov_e: float
+    jk_cov_m: float
+    jk_cov_c_v: float
+    jk_cov_chi: float
 
 
 def observables(L: int, beta: float, E: np.ndarray, M: np.ndarray):
@@ -382,6 +392,10 @@ class OracleRun:
         self.E, self.M = energy_magnetisation(L, self.spins)
         with mpmath.workprec(PREC_BITS):
             self._acc = self.N * mpmath.log(2)  # ln Z_{beta_0} = L^2 ln 2
+            # jackknife samples of -beta F, one per block of the free-energy jackknife
+            self.n_F = blocking.n_blocks_free_energy(R)
+            self._jk = [self._acc] * self.n_F
+        self._jk_lnq = None
         self.last_counts = np.zeros(0, dtype=np.int32)
         self.records: List[Record] = [self._record(0.0, 0, 0.0)]
 
@@ -393,8 +407,9 @@ class OracleRun:
         R_i = len(self.E)
         rho_step = float(Fraction(sum_cnt2, R_i)) if self.step > 0 else 0.0
         errs = blocking.population_errors(self.L, beta, self.E, self.M)
+        jk = blocking.free_energy_errors(self.L, beta, self.E, self.M, self._jk, self.n_F)
         return Record(self.step, beta, R_i, *sums, *obs, float(ln_q), float(self._acc),
-                      f, sum_c2, int(sum_cnt2), rho_t, rho_s, rho_step, *errs)
+                      f, sum_c2, int(sum_cnt2), rho_t, rho_s, rho_step, *errs, *jk)
 
     # -- step 2 of the algorithm ------------------------------------------------
     def copy_counts(self, beta_prev: float, beta_next: float, step: int):
@@ -408,6 +423,7 @@ class OracleRun:
                 boltz[int(e)] = mpmath.exp(-db * int(e))
             Q = mpmath.fsum(boltz[int(e)] for e in E) / Rp  # Eq. (Q)
             ln_q = mpmath.log(Q)
+            self._jk_lnq = blocking.leave_one_block_out_ln_q(E, boltz, self.n_F)
             if self.resample == "none":
                 return np.ones(Rp, dtype=np.int32), ln_q
             if self.resample == "poisson":
@@ -469,6 +485,7 @@ class OracleRun:
         self.last_counts = counts
         with mpmath.workprec(PREC_BITS):
             self._acc = self._acc + ln_q
+            self._jk = [a + b for a, b in zip(self._jk, self._jk_lnq)]
         self.step = i
         if self.update == "heatbath":
             thr5 = [heatbath_threshold(beta, dE) for dE in (-8, -4, 0, 4, 8)]
@@ -495,6 +512,8 @@ class OracleRun:
         self.E, self.M = energy_magnetisation(self.L, self.spins)
         with mpmath.workprec(PREC_BITS):
             self._acc = mpmath.mpf(acc)
+            # the jackknife starts again from the adopted population
+            self._jk = [self._acc] * self.n_F
         if betas is not None:
             self.betas = [float(b) for b in betas]
 
