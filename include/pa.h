@@ -126,6 +126,21 @@ typedef struct pa_obs {
     double err_m;         /* blocked standard error of m */
     double err_c_v;       /* jackknife standard error of c_v */
     double err_chi;       /* jackknife standard error of chi */
+    /* Single-run jackknife of the free-energy estimator (Sec. "Conclusions",
+     * last guideline: variance and covariances involving the free-energy
+     * estimator from a jackknife block analysis of the tree-ordered population;
+     * Eqs. free-emergy-estimator, jackknife-variance, bias_covariance).  Sample
+     * k of -beta_i F_i leaves block k out of every normalisation Q_l, l <= i:
+     * block k of the parents of step l is the slot range [floor(k R_{l-1} / n_F),
+     * floor((k + 1) R_{l-1} / n_F)) with n_F = min(100, R) for the whole run (the
+     * same index range of the tree-ordered populations, so the same lineages).
+     * jk_var_beta_F = (n_F - 1)/n_F sum_k (beta F_k - mean)^2 (0 at step 0);
+     * jk_cov_O = (n_F - 1)/n_F sum_k (O_k^J - mean O^J)(beta F_k - mean), O_k^J
+     * the jackknife sample of e, m, c_v or chi of the current population without
+     * its block k (NaN unless min(100, R_i) = n_F).  NaN when n_F < 2.  After
+     * pa_set_population the samples start again from the adopted population. */
+    double jk_var_beta_F;
+    double jk_cov_e, jk_cov_m, jk_cov_c_v, jk_cov_chi;
 } pa_obs;
 
 typedef struct pa_ctx pa_ctx;

@@ -237,7 +237,7 @@ void oracle_sweeps(uint64_t seed, int L, int R, int8_t *spins, int step, int the
     int half = L / 2;
     for (int sweep = 0; sweep < theta; ++sweep) {
         for (int colour = 0; colour < 2; ++colour) {
-            uint32_t h = (uint32_t)(2 * (theta * (step - 1) + sweep) + colour);
+            uint32_t h = 2u * ((uint32_t)theta * (uint32_t)(step - 1) + (uint32_t)sweep) + (uint32_t)colour;
             for (int r0 = 0; r0 < R; r0 += 64) {
                 int n_lanes = R - r0 < 64 ? R - r0 : 64;
                 uint32_t g = (uint32_t)((slot0 + r0) / 64);
@@ -302,7 +302,7 @@ void oracle_sweeps_heatbath(uint64_t seed, int L, int R, int8_t *spins, int step
     int half = L / 2;
     for (int sweep = 0; sweep < theta; ++sweep) {
         for (int colour = 0; colour < 2; ++colour) {
-            uint32_t h = (uint32_t)(2 * (theta * (step - 1) + sweep) + colour);
+            uint32_t h = 2u * ((uint32_t)theta * (uint32_t)(step - 1) + (uint32_t)sweep) + (uint32_t)colour;
             for (int r0 = 0; r0 < R; r0 += 64) {
                 int n_lanes = R - r0 < 64 ? R - r0 : 64;
                 uint32_t g = (uint32_t)((slot0 + r0) / 64);

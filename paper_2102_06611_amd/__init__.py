@@ -56,7 +56,9 @@ class pa_obs(ctypes.Structure):
                 ("rho_t_step", ctypes.c_double), ("r_eff_E", ctypes.c_double),
                 ("r_eff_absM", ctypes.c_double), ("err_e", ctypes.c_double),
                 ("err_m", ctypes.c_double), ("err_c_v", ctypes.c_double),
-                ("err_chi", ctypes.c_double)]
+                ("err_chi", ctypes.c_double), ("jk_var_beta_F", ctypes.c_double),
+                ("jk_cov_e", ctypes.c_double), ("jk_cov_m", ctypes.c_double),
+                ("jk_cov_c_v", ctypes.c_double), ("jk_cov_chi", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -43,6 +43,14 @@ bool validate(const pa_config &c, std::string *why) {
     if (c.n_steps < 0 || c.n_steps > 10000000) return fail("n_steps must be in [0, 1e7]");
     if (c.theta < 0 || c.theta > 1000000) return fail("theta must be in [0, 1e6]");
     if (c.resample < 0 || c.resample > 3) return fail("unknown resampling rule");
+    // multinomial: the quantised weights are at most 2^40 each, so their total
+    // over R parents stays below 2^63 (signed 64-bit block sums) for R < 2^23
+    if (c.resample == PA_RESAMPLE_MULTINOMIAL && c.R >= (1 << 23))
+        return fail("multinomial resampling needs R < 2^23 (64-bit total of the 2^40-quantised weights)");
+    // the global half-sweep index 2 (theta (i - 1) + s) + colour is a 32-bit Philox
+    // counter word: it must not wrap over the run's steps
+    if (2 * (int64_t)c.theta * (int64_t)c.n_steps > (int64_t)1 << 32)
+        return fail("2 theta n_steps must not exceed 2^32 (half-sweep counter of the random stream)");
     if (c.layout < 0 || c.layout > 1) return fail("unknown layout");
     if (c.capacity < 0) return fail("capacity must be >= 0");
     if (c.capacity > 0 && c.capacity < c.R) return fail("capacity must be >= R");
@@ -62,7 +70,7 @@ struct RunPlan {
     int L, N, R, C, G, K, nblk, max_steps;
     size_t off_ms[2], off_s8[2], off_E, off_M, off_fam[2], off_hist, off_zlev, off_wlev,
         off_plev, off_cnt, off_off, off_par, off_cum, off_part, off_partd, off_blk, off_betas, off_records, off_st,
-        off_stage, off_feat, off_flog, off_tlog, off_alog, off_alpha;
+        off_stage, off_feat, off_flog, off_tlog, off_alog, off_alpha, off_jkw;
     size_t bytes;
 };
 
@@ -116,6 +124,7 @@ RunPlan plan_run(const pa_config &c) {
     p.off_tlog = take((size_t)(p.max_steps + 1) * sizeof(float));
     p.off_alog = take((size_t)(p.max_steps + 1) * sizeof(int32_t));
     p.off_alpha = take((size_t)(p.max_steps + 1) * sizeof(double));
+    p.off_jkw = take((size_t)kBlocks * sizeof(double));
     p.bytes = o;
     return p;
 }
@@ -373,6 +382,7 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         d.tgt_log = (float *)(base + p.off_tlog);
         d.acc_log = (int32_t *)(base + p.off_alog);
         d.alpha_log = (double *)(base + p.off_alpha);
+        d.jkw = (double *)(base + p.off_jkw);
         RunState &s = states[r];
         std::memset(&s, 0, sizeof s);
         s.step = -1;
@@ -739,7 +749,7 @@ pa_status pa_get_state(pa_ctx *ctx, void *buf, size_t cap, size_t *used) {
     char *p = (char *)buf;
     StateHeader h;
     std::memset(&h, 0, sizeof h);
-    std::memcpy(h.magic, "PASTATE2", 8);
+    std::memcpy(h.magic, "PASTATE3", 8);
     h.L = d.L; h.R = d.R; h.C = d.C; h.layout = d.layout; h.resample = d.resample;
     h.max_steps = d.max_steps; h.theta = d.theta; h.step = s.step; h.R_i = s.R_cur;
     h.update = d.update;
@@ -768,7 +778,7 @@ pa_status pa_set_state(pa_ctx *ctx, const void *buf, size_t len) {
     if (len < sizeof(StateHeader)) return fail(B, PA_ERR_STATE, "snapshot too short");
     StateHeader h;
     std::memcpy(&h, p, sizeof h); p += sizeof h;
-    if (std::memcmp(h.magic, "PASTATE2", 8) || h.L != d.L || h.R != d.R || h.C != d.C ||
+    if (std::memcmp(h.magic, "PASTATE3", 8) || h.L != d.L || h.R != d.R || h.C != d.C ||
         h.layout != d.layout || h.resample != d.resample || h.max_steps != d.max_steps ||
         h.theta != d.theta || h.update != d.update || h.seed != B->cfg[0].seed)
         return fail(B, PA_ERR_STATE, "snapshot belongs to another configuration");
@@ -777,21 +787,59 @@ pa_status pa_set_state(pa_ctx *ctx, const void *buf, size_t len) {
     if (len != snapshot_bytes(d, h.step, h.R_i)) return fail(B, PA_ERR_STATE, "snapshot size mismatch");
     RunState s;
     std::memcpy(&s, p, sizeof s); p += sizeof s;
-    if (s.cur < 0 || s.cur > 1 || s.R_cur != h.R_i || s.step != h.step || s.err != 0)
+    if (s.cur < 0 || s.cur > 1 || s.R_cur != h.R_i || s.step != h.step || s.err != 0 ||
+        s.r_parents < 0 || s.r_parents > d.C || !std::isfinite(s.acc_hi) || !std::isfinite(s.acc_lo))
         return fail(B, PA_ERR_STATE, "snapshot state is inconsistent");
-    PA_HIP(B, hipStreamSynchronize(B->stream));
+    for (int k = 0; k < kBlocks; ++k)
+        if (!std::isfinite(s.jk_F[k])) return fail(B, PA_ERR_STATE, "snapshot state is inconsistent");
+    // the fields below are derived during a step: nothing of the snapshot's is kept
+    s.R_new = s.R_cur;
+    s.err_step = 0;
+    s.kmin = INT32_MAX;
+    s.kmax = -1;
+    s.lnq_hi = s.lnq_lo = 0.0;
+    s.w_total = 0;
+    s.sum_cnt2 = 0;
+    // family labels, energies and magnetisations are checked before anything
+    // reaches the device (the energies index the histogram there): labels are
+    // beta_0 replica indices in tree order (non-decreasing), E in [-2N, 2N] with
+    // E = 2N mod 4, M in [-N, N] with M = N mod 2
     const size_t pop = (size_t)(s.R_cur + 63) / 64 * group_bytes(d);
+    const size_t n4 = (size_t)s.R_cur * 4;
+    std::vector<int32_t> fam(s.R_cur), E(s.R_cur), M(s.R_cur);
+    std::memcpy(fam.data(), p + pop, n4);
+    std::memcpy(E.data(), p + pop + n4, n4);
+    std::memcpy(M.data(), p + pop + 2 * n4, n4);
+    for (int j = 0; j < s.R_cur; ++j) {
+        if (fam[j] < 0 || fam[j] >= d.R || (j > 0 && fam[j] < fam[j - 1]))
+            return fail(B, PA_ERR_STATE, "snapshot family labels are not in tree order");
+        if (E[j] < -2 * d.N || E[j] > 2 * d.N || (E[j] + 2 * d.N) % 4 != 0 || M[j] < -d.N ||
+            M[j] > d.N || (M[j] + d.N) % 2 != 0)
+            return fail(B, PA_ERR_STATE, "snapshot energies or magnetisations out of range");
+    }
+    PA_HIP(B, hipStreamSynchronize(B->stream));
     void *dst = d.layout == PA_LAYOUT_MSC64 ? (void *)d.ms[s.cur] : (void *)d.s8[s.cur];
     PA_HIP(B, hipMemcpy(d.st, &s, sizeof s, hipMemcpyHostToDevice));
     PA_HIP(B, hipMemcpy(dst, p, pop, hipMemcpyHostToDevice)); p += pop;
-    const size_t n4 = (size_t)s.R_cur * 4;
-    PA_HIP(B, hipMemcpy(d.fam[s.cur], p, n4, hipMemcpyHostToDevice)); p += n4;
-    PA_HIP(B, hipMemcpy(d.E, p, n4, hipMemcpyHostToDevice)); p += n4;
-    PA_HIP(B, hipMemcpy(d.M, p, n4, hipMemcpyHostToDevice)); p += n4;
+    PA_HIP(B, hipMemcpy(d.fam[s.cur], p, n4, hipMemcpyHostToDevice)); p += 3 * n4;
     PA_HIP(B, hipMemcpy(d.betas, p, (size_t)(d.max_steps + 1) * 8, hipMemcpyHostToDevice));
     std::memcpy(B->betas[0].data(), p, (size_t)(d.max_steps + 1) * 8);
     p += (size_t)(d.max_steps + 1) * 8;
     PA_HIP(B, hipMemcpy(d.records, p, (size_t)(s.step + 1) * sizeof(pa_obs), hipMemcpyHostToDevice));
+    // E and M are measured again from the restored spins and must equal the
+    // snapshot's: a snapshot whose spins do not fit its energies is rejected
+    PA_HIP(B, launch_swap_buffers(B->lc, 0));
+    PA_HIP(B, launch_sweeps(B->lc, 1));
+    PA_HIP(B, launch_swap_buffers(B->lc, 0));
+    PA_HIP(B, hipStreamSynchronize(B->stream));
+    std::vector<int32_t> E2(s.R_cur), M2(s.R_cur);
+    PA_HIP(B, hipMemcpy(E2.data(), d.E, n4, hipMemcpyDeviceToHost));
+    PA_HIP(B, hipMemcpy(M2.data(), d.M, n4, hipMemcpyDeviceToHost));
+    if (E2 != E || M2 != M) {
+        PA_HIP(B, launch_set_error(B->lc, 0, PA_ERR_STATE));  // no valid run is left
+        PA_HIP(B, hipStreamSynchronize(B->stream));
+        return fail(B, PA_ERR_STATE, "snapshot energies do not match its spins");
+    }
     PA_HIP(B, launch_hist_current(B->lc));  // the next step reads the histogram
     PA_HIP(B, hipStreamSynchronize(B->stream));
     B->host_step[0] = s.step;

@@ -55,6 +55,11 @@ struct RunState {
     int32_t reserved;            // 0
     unsigned long long philox_calls;  // Philox calls counted by the sweeps (profiling)
     unsigned long long sweep_words;   // 64-replica words updated by the sweeps
+    double s_hi, s_lo;                // S = sum_l n_l w_l of the step in progress (Eq. Q)
+    // free-energy jackknife: for block k of the n_F = min(kBlocks, R) blocks,
+    // sum over the steps so far of ln Q^(k) - ln Q (Q without block k of the
+    // parents, Eq. Q), so that sample k of -beta F is -beta F + jk_F[k]
+    double jk_F[kBlocks];
 };
 
 // Static description of one run plus pointers into its slice of the workspace.
@@ -89,6 +94,7 @@ struct RunDesc {
     float *tgt_log;            // [max_steps + 1] log(dbeta* sigma_E) of each step
     int32_t *acc_log;          // [max_steps + 1] learned proposal taken
     double *alpha_log;         // [max_steps + 1] overlap of the step taken
+    double *jkw;               // [kBlocks] parents' weight sum per free-energy jackknife block
 };
 
 // Maps a flat block index of a batched launch to (run, item within the run).

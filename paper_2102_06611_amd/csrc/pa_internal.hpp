@@ -53,6 +53,8 @@ hipError_t launch_resample(const LaunchCtx &c);
 hipError_t launch_hist_current(const LaunchCtx &c);
 hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta);
 hipError_t launch_set_beta(const LaunchCtx &c, int r, int idx, double beta);
+hipError_t launch_swap_buffers(const LaunchCtx &c, int r);
+hipError_t launch_set_error(const LaunchCtx &c, int r, int status);
 hipError_t launch_unpack_group(const LaunchCtx &c, int r, int g, int N);
 hipError_t launch_pack_group(const LaunchCtx &c, int r, int g, int buf, int n_valid, int N);
 hipError_t launch_adopt_begin(const LaunchCtx &c, int r, int R_i);

@@ -290,6 +290,8 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
         }
         st->lnq_hi = lnq.hi;
         st->lnq_lo = lnq.lo;
+        st->s_hi = S.hi;
+        st->s_lo = S.lo;
     }
     bool amb = false;
     const double R2_32 = ldexp((double)rd.R, 32);
@@ -339,6 +341,34 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
         st->err = PA_ERR_NUMERIC;
         st->err_step = i;
     }
+}
+
+// ------------------------------------------------------------------ free-energy jackknife
+
+// Sec. "Conclusions" (last guideline) with Eq. free-emergy-estimator: sample k
+// of the jackknife of -beta F leaves block k of every parent population out
+// of every Q.  Block k of the population entering step i is the slot range
+// [floor(k R_{i-1} / n_F), floor((k + 1) R_{i-1} / n_F)) of the tree-ordered
+// population, n_F = min(kBlocks, R) for the whole run.  One workgroup per
+// (run, block) sums the parents' weights w = e^{-dbeta (E - E_min)} of its
+// block (the level weights of k_norm) in a fixed order; k_record turns the
+// sums into ln Q^(k) - ln Q = ln(1 - W_k / S) - ln(1 - B_k / R_{i-1}).
+__global__ void __launch_bounds__(256) k_jack_weights(const RunDesc *runs) {
+    const RunDesc &rd = runs[blockIdx.x / kBlocks];
+    const int k = blockIdx.x % kBlocks;
+    RunState *st = rd.st;
+    const int nF = min(kBlocks, rd.R);
+    if (st->err || k >= nF) return;
+    __shared__ double shd[16];
+    const int Rp = st->R_cur, kmin = st->kmin;
+    const int lo = (int)((int64_t)k * Rp / nF), hi = (int)((int64_t)(k + 1) * Rp / nF);
+    double s = 0.0;
+    for (int j = lo + (int)threadIdx.x; j < hi; j += blockDim.x) {
+        const int l = ((rd.E[j] + 2 * rd.N) >> 2) - kmin;
+        s += rd.wlev[2 * l];
+    }
+    const double t = block_sum_f64(s, shd);
+    if (threadIdx.x == 0) rd.jkw[k] = t;
 }
 
 // ------------------------------------------------------------------ copy counts
@@ -1716,7 +1746,7 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
     uint32_t calls = 0, wcalls = 0;
     for (int s = 0; s < theta; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
-            const uint32_t h = 2u * (uint32_t)(theta * (i - 1) + s) + (uint32_t)colour;
+            const uint32_t h = 2u * ((uint32_t)theta * (uint32_t)(i - 1) + (uint32_t)s) + (uint32_t)colour;
             WordWalk wk = walk_start(tid, hl);
             // next row of this thread's column (kWalkOneGroup): with dy1 odd the
             // site alternates between the two columns 2 xh1 and 2 xh1 + 1
@@ -2086,11 +2116,32 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     // replicas).  Each enters as its difference d from the value of the whole
     // population, so that sum (x - mean x)^2 = sum d^2 - (sum d)^2 / n is formed
     // from small numbers in one pass.
+    // free-energy jackknife (Sec. "Conclusions", last guideline; Eqs.
+    // free-emergy-estimator, jackknife-variance, bias_covariance): thread k < n_F
+    // adds this step's ln Q^(k) - ln Q to its running sum D_k; sample k of
+    // beta F is beta F - D_k
     __shared__ int64_t tot_sh[4];
-    __shared__ double bdev[kBlocks][8], dsum[8];
+    __shared__ double bdev[kBlocks][16], dsum[16], dF[kBlocks];
+    const int nF = min(kBlocks, rd.R);
+    if ((int)threadIdx.x < nF) {
+        const int k = threadIdx.x;
+        double D = st->jk_F[k];
+        if (step > 0) {
+            const int Rp = st->R_cur;  // the parents of this step
+            const int64_t lo = (int64_t)k * Rp / nF, hi = (int64_t)(k + 1) * Rp / nF;
+            const double S = st->s_hi + st->s_lo;
+            D += hi - lo == Rp ? __builtin_nan("")
+                               : log1p(-rd.jkw[k] / S) - log1p(-(double)(hi - lo) / (double)Rp);
+            st->jk_F[k] = D;
+        }
+        dF[k] = D;
+    }
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) tot_sh[q] = T[q];
     __syncthreads();
+    double Dbar = 0.0;  // mean of the D_k, in block order (every thread)
+    for (int k = 0; k < nF; ++k) Dbar += dF[k];
+    Dbar /= nF;
     const double Rd = (double)Rn;
     const double whole[4] = {
         (double)tot_sh[0] / Rd, (double)tot_sh[2] / Rd,
@@ -2111,11 +2162,29 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
             bdev[k][2 * q] = d;
             bdev[k][2 * q + 1] = d * d;
         }
+        // jackknife samples of e and m less the whole population's value:
+        // (T B_k - R b_k) / (R (R - B_k) N), b_k the block's sum
+        const double den = Rd * (double)nk * Nd;
+        const double ej = (double)((__int128)tot_sh[0] * Bk - (__int128)Rn * bs[0]) / den;
+        const double mj = (double)((__int128)tot_sh[2] * Bk - (__int128)Rn * bs[2]) / den;
+        // deviation of sample k of beta F from the samples' mean
+        const double db = k < nF ? -(dF[k] - Dbar) : 0.0;
+        bdev[k][8] = ej;
+        bdev[k][9] = ej * db;
+        bdev[k][10] = mj;
+        bdev[k][11] = mj * db;
+        bdev[k][12] = bdev[k][4] * db;
+        bdev[k][13] = bdev[k][6] * db;
+    }
+    if ((int)threadIdx.x < nF) {
+        const double db = -(dF[threadIdx.x] - Dbar);
+        bdev[threadIdx.x][14] = db * db;
     }
     __syncthreads();
-    if (threadIdx.x < 8) {  // eight sums over the blocks, each in block order
+    if (threadIdx.x < 16) {  // sums over the blocks, each in block order
+        const int n = threadIdx.x == 14 ? nF : nbk;
         double t = 0.0;
-        for (int k = 0; k < nbk; ++k) t += bdev[k][threadIdx.x];
+        for (int k = 0; k < n; ++k) t += bdev[k][threadIdx.x];
         dsum[threadIdx.x] = t;
     }
     __syncthreads();
@@ -2163,6 +2232,16 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
         o.err_c_v = sqrt(jf * ss[2]);
         o.err_chi = sqrt(jf * ss[3]);
     }
+    // the deviations of the beta F samples sum to zero, so each covariance is
+    // (n - 1)/n sum_k (O_k^J - O) (beta F_k^J - mean): the offset of O drops out
+    const double NaN = __builtin_nan("");
+    const double jfF = (double)(nF - 1) / (double)nF;
+    o.jk_var_beta_F = nF < 2 ? NaN : jfF * dsum[14];
+    const bool cov = nF >= 2 && nbk == nF;
+    o.jk_cov_e = cov ? jfF * dsum[9] : NaN;
+    o.jk_cov_m = cov ? jfF * dsum[11] : NaN;
+    o.jk_cov_c_v = cov ? jfF * dsum[12] : NaN;
+    o.jk_cov_chi = cov ? jfF * dsum[13] : NaN;
     rd.records[step] = o;
     st->r_parents = step == 0 ? 0 : st->R_cur;
     st->step = step;
@@ -2220,6 +2299,23 @@ __global__ void k_adopt_end(const RunDesc *runs, int r, int step, double acc) {
     st->R_cur = st->R_new;
     st->acc_hi = acc;
     st->acc_lo = 0.0;
+    for (int k = 0; k < kBlocks; ++k) st->jk_F[k] = 0.0;  // the jackknife starts again here
+}
+
+// Swap the roles of the two population buffers (R_new = R_cur), so that an
+// init-mode sweep launch measures E and M of the current population; a second
+// call restores them.  Used to re-derive E and M of a restored snapshot.
+__global__ void k_swap_buffers(const RunDesc *runs, int r) {
+    RunState *st = runs[r].st;
+    st->R_new = st->R_cur;
+    st->cur ^= 1;
+}
+
+// Mark run r as holding no valid state (a rejected snapshot).
+__global__ void k_set_error(const RunDesc *runs, int r, int status) {
+    RunState *st = runs[r].st;
+    st->err = status;
+    st->err_step = st->step + 1;
 }
 
 __global__ void k_set_beta(const RunDesc *runs, int r, int idx, double beta) {
@@ -2604,6 +2700,7 @@ hipError_t launch_weighted(const LaunchCtx &c, int first, int count, pa_weighted
 
 hipError_t launch_counts(const LaunchCtx &c) {
     PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
+    PA_LAUNCH(k_jack_weights, dim3(c.n_runs * kBlocks), dim3(256), 0, c.stream, c.runs);
     if (c.any_nearest)
         PA_LAUNCH(k_counts_nearest, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
@@ -2655,6 +2752,16 @@ hipError_t launch_hist_current(const LaunchCtx &c) {
 
 hipError_t launch_overlap(const LaunchCtx &c, int r, double dbeta) {
     PA_LAUNCH(k_overlap, dim3(1), dim3(256), 0, c.stream, c.runs, r, dbeta);
+    return hipSuccess;
+}
+
+hipError_t launch_swap_buffers(const LaunchCtx &c, int r) {
+    PA_LAUNCH(k_swap_buffers, dim3(1), dim3(1), 0, c.stream, c.runs, r);
+    return hipSuccess;
+}
+
+hipError_t launch_set_error(const LaunchCtx &c, int r, int status) {
+    PA_LAUNCH(k_set_error, dim3(1), dim3(1), 0, c.stream, c.runs, r, status);
     return hipSuccess;
 }
 

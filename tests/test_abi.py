@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     # pa_config: 3 int32 + pointer + 2 int32 + uint64 + 4 int32 (with padding)
     assert ctypes.sizeof(pa.pa_config) == 48
-    assert ctypes.sizeof(pa.pa_obs) == 8 + 8 + 4 * 8 + 4 * 8 + 2 * 8 + 3 * 8 + 3 * 8 + 6 * 8
+    assert ctypes.sizeof(pa.pa_obs) == 8 + 8 + 4 * 8 + 4 * 8 + 2 * 8 + 3 * 8 + 3 * 8 + 6 * 8 + 5 * 8
     assert ctypes.sizeof(pa.pa_weighted) == 8 + 8 + 20 * 8
 
 
@@ -69,7 +69,12 @@ def test_workspace_size_scales_with_layout_and_population():
 @pytest.mark.parametrize("bad", [dict(L=7), dict(L=2), dict(L=130), dict(R=0), dict(theta=-1),
                                  dict(resample="bogus"), dict(update="bogus"), dict(capacity=10),
                                  dict(betas=[0.1, 0.2]), dict(betas=[0.0, 0.3, 0.2]),
-                                 dict(betas=[0.0, float("nan")])])
+                                 dict(betas=[0.0, float("nan")]),
+                                 # the 2^40-quantised multinomial weights of 2^23 parents
+                                 # would reach 2^63
+                                 dict(R=1 << 23, resample="multinomial"),
+                                 # the 32-bit half-sweep counter would wrap: 2 theta n = 2^32 + 2e5
+                                 dict(theta=100000, betas=np.linspace(0, 0.4, 21476 + 1))])
 def test_invalid_configurations_are_rejected(bad):
     if bad.get("resample") == "bogus":
         cfg, arr = _cfg()
@@ -82,6 +87,14 @@ def test_invalid_configurations_are_rejected(bad):
     st, _ = _ws(cfg)
     assert st == pa.PA_ERR_ARG
     assert pa.lib().pa_last_error(None)
+
+
+def test_limits_are_inclusive():
+    # the largest multinomial population and the longest counter range are accepted
+    cfg, arr = _cfg(R=(1 << 23) - 1, resample="multinomial")
+    assert _ws(cfg)[0] == pa.PA_OK
+    cfg, arr = _cfg(theta=1 << 16, betas=np.linspace(0, 0.4, (1 << 15) + 1))
+    assert _ws(cfg)[0] == pa.PA_OK
 
 
 def test_create_rejects_missing_or_small_workspace_before_touching_the_device():

@@ -29,6 +29,13 @@ FP_FIELDS = ("beta", "e", "c_v", "m", "chi", "ln_Q", "minus_beta_F", "rho_t", "r
 # a block mean is rounded to ~1e-16 relative and enters differences about 1e-3
 # of its size, so the results agree to ~1e-12; 1e-9 leaves a margin
 BLOCK_FIELDS = ("r_eff_E", "r_eff_absM", "err_e", "err_m", "err_c_v", "err_chi")
+# free-energy jackknife: the device sums each step's ln Q^(k) - ln Q =
+# ln(1 - W_k / S) - ln(1 - B_k / R_{i-1}) in binary64 (W_k a binary64 sum of
+# level weights, S double-double), about 1e-13 relative per step against the
+# oracle's 256-bit samples; a covariance can cancel to far below its terms, so
+# it is compared on the scale of its Cauchy-Schwarz bound sigma_O sigma_F
+JK_COV = (("jk_cov_e", "err_e"), ("jk_cov_m", "err_m"), ("jk_cov_c_v", "err_c_v"),
+          ("jk_cov_chi", "err_chi"))
 
 
 def log(*a):
@@ -57,6 +64,21 @@ def check_record(got: dict, want, ctx=""):
         assert close(got[k], getattr(want, k)), (ctx, k, got[k], getattr(want, k))
     for k in BLOCK_FIELDS:
         assert close(got[k], getattr(want, k), 1e-9), (ctx, k, got[k], getattr(want, k))
+    check_jackknife(got, want, ctx)
+
+
+def check_jackknife(got: dict, want, ctx=""):
+    vF = want.jk_var_beta_F
+    assert close(got["jk_var_beta_F"], vF, 1e-9), (ctx, got["jk_var_beta_F"], vF)
+    for k, err in JK_COV:
+        a, b = got[k], getattr(want, k)
+        if math.isnan(b) or math.isnan(a):
+            assert math.isnan(a) and math.isnan(b), (ctx, k, a, b)
+            continue
+        scale = math.sqrt(vF) * getattr(want, err) if vF > 0 else 0.0
+        if math.isnan(scale):
+            scale = 0.0
+        assert abs(a - b) <= 1e-9 * (abs(b) + scale), (ctx, k, a, b, scale)
 
 
 def check_population(run: "pa.Run", ref: po.OracleRun, ctx=""):
