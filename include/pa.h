@@ -397,6 +397,26 @@ pa_status pa_learned_dbeta(pa_ctx *ctx, const float *dev_params, double alpha_mi
                            double alpha_target, double dbeta_max, float *dev_feat,
                            double *dbeta, int32_t *accepted);
 
+/* ---- allocation-free variant ---------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * answer as pa_adaptive_dbeta, for a population given as its energies instead
+ * of a handle, with no workspace and no allocation.  dev_E[0..n) are the
+ * energies E_j = -sum_<ij> s_i s_j of n replicas of an L x L torus (device
+ * memory, any order); dev_out[0] receives the largest dbeta in (0, dbeta_max]
+ * whose histogram overlap is >= alpha_target and dev_out[1] that overlap
+ * (device memory, two doubles; both NaN when an energy is not -2 L^2 + 4k
+ * with 0 <= k <= L^2).  Asynchronous on stream, which belongs to the current
+ * device, as do dev_E and dev_out.  The energy histogram lives in a
+ * library-owned scratch array of 16448 + 64 int32 (66 KiB) per device, kept
+ * until the process ends and cleared by every call, so L is limited to 128
+ * (PA_ERR_ARG beyond, or for odd L, n < 1, alpha_target outside (0, 1), or
+ * dbeta_max not finite and positive).  Calls that overlap in time on one
+ * device share that array and race: serialise them (one stream, or events). */
+pa_status pa_adaptive_dbeta_noalloc(const int32_t *dev_E, int32_t n, int32_t L,
+                                    double alpha_target, double dbeta_max, double *dev_out,
+                                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

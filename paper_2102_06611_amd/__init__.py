@@ -101,6 +101,7 @@ SIGNATURES = {
     "pa_set_population": (_i32, [_vp, _i32, _i32, _P(ctypes.c_int8), _P(_i32), _dbl]),
     "pa_overlap": (_i32, [_vp, _dbl, _P(_dbl)]),
     "pa_adaptive_dbeta": (_i32, [_vp, _dbl, _dbl, _P(_dbl)]),
+    "pa_adaptive_dbeta_noalloc": (_i32, [_vp, _i32, _i32, _dbl, _dbl, _vp, _vp]),
     "pa_destroy": (None, [_vp]),
     "pa_last_error": (ctypes.c_char_p, [_vp]),
     "pa_batch_workspace_size": (_i32, [_P(pa_config), _i32, _P(ctypes.c_size_t)]),
@@ -448,3 +449,13 @@ def mlp_train_step(params, adam, x, t, lr: float, step: int, loss, stream=None):
                                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
                                    x.shape[0], float(lr), int(step), ctypes.c_void_p(loss.data_ptr()),
                                    _stream_handle(stream)))
+
+
+def adaptive_dbeta_noalloc(E_dev, L: int, alpha_target: float, dbeta_max: float, out_dev,
+                           stream=None):
+    """pa_adaptive_dbeta_noalloc: out_dev[0] = dbeta, out_dev[1] = its overlap, for
+    the energies in the int32 device tensor E_dev (asynchronous)."""
+    _check(lib().pa_adaptive_dbeta_noalloc(ctypes.c_void_p(E_dev.data_ptr()), E_dev.numel(),
+                                           int(L), float(alpha_target), float(dbeta_max),
+                                           ctypes.c_void_p(out_dev.data_ptr()),
+                                           _stream_handle(stream)))

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpa.so")
-SOURCES = ["pa_kernels.hip", "pa_mlp.hip", "pa_api.hip"]
+SOURCES = ["pa_kernels.hip", "pa_mlp.hip", "pa_api.hip", "pa_noalloc.hip"]
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1187,3 +1187,6 @@ pa_status pa_philox4x32_10(uint32_t key0, uint32_t key1, const uint32_t *dev_ctr
 }
 
 }  // extern "C"
+
+// Message of a failing handle-free call made outside this file (pa_last_error(NULL)).
+void pa::set_last_error(const char *msg) { g_last_error = msg; }

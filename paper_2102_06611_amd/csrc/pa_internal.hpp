@@ -38,6 +38,7 @@ struct LaunchCtx {
     bool count_calls = false;  // sweeps count the Philox calls the words need (pa_profile 3)
 };
 
+void set_last_error(const char *msg);  // for pa_last_error(NULL)
 hipError_t configure_kernels();
 size_t sweep_lds_bytes(int L, int gpb);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
