@@ -76,6 +76,12 @@ def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial"
     wall = time.perf_counter() - t0
     recs = [run.observables(i) for i in range(K + 1)]
     attempts = sum(r["R_i"] for r in recs[1:]) * L * L * THETA
+    # the rest of the schedule, untimed: the free-energy error at its end
+    n_total = len(betas) - 1
+    if K < n_total:
+        run.run(n_total - K)
+        run.sync()
+    final = run.observables(n_total)
     # the same K steps again with phase timing, then once more counting the
     # Philox calls (counting slows the sweeps; the runs are deterministic:
     # same populations, same calls)
@@ -97,6 +103,7 @@ def time_layout(pa, torch, betas, layout, K, W, L=L, R=R, resample="multinomial"
         else:
             prof["philox_calls"], prof["sweep_words"] = p["philox_calls"], p["sweep_words"]
     prof["geometry"] = list(geometry)
+    prof["final"] = final
     return run, wall, prof, recs, attempts
 
 
@@ -158,6 +165,54 @@ def time_weighted(pa, torch, M=64, L=32, R=2000, n=200):
             "us_per_call_all_steps": wall * 1e6,
             "at_last_step": {k: last[k] for k in ("e", "e_plain", "c_v", "c_v_plain", "n_eff_runs",
                                                   "var_beta_F", "rho_f", "cov_e")}}
+
+
+def compare_schedules(pa, torch, n_seeds=16):
+    """Plain linear vs self-adaptive vs learned temperature steps at L = 128,
+    R = 100000, beta 0 -> 1.0, theta = 10, nearest-integer resampling, on the
+    same seeds: steps taken and |(-beta F) - ln Z_exact| / L^2 at beta = 1.0.
+    The network is trained on the device from adaptive runs at L = 32 and 64,
+    R = 20000 (error-budget targets, paper_2102_06611_amd/schedules.py)."""
+    import numpy as np
+    from paper_2102_06611_amd import schedules
+    from workloads import linear_schedule
+    exact = json.load(open(os.path.join(ROOT, "tests", "golden", "exact_lnz.json")))
+    ln_z = exact["points"]["L128_1"]
+    t0 = time.perf_counter()
+    info = []
+    X, t = schedules.collect((32, 64), 20000, range(500, 508), THETA, 0.85, 1.0, info=info)
+    params, losses = schedules.train(X, t, iters=4000, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    seeds = [900 + k for k in range(n_seeds)]
+    res = schedules.compare(params, 128, 100_000, THETA, seeds, ln_z)
+    plain = []
+    betas = linear_schedule(1.0, 400)
+    for sd in seeds:
+        r = pa.Run(128, 100_000, betas, THETA, sd, "nearest", "msc64")
+        r.run(400)
+        plain.append(abs(r.observables(400)["minus_beta_F"] - ln_z) / (128 * 128))
+        r.close()
+
+    def stats(x):
+        x = np.asarray(x, dtype=np.float64)
+        return {"mean": float(x.mean()), "se": float(x.std(ddof=1) / math.sqrt(len(x)))}
+    sa = [r["steps_adaptive"] for r in res]
+    sl = [r["steps_learned"] for r in res]
+    return {
+        "workload": "L=128, R=100000, beta 0->1.0, theta=10, nearest, msc64, %d seeds; "
+                    "network trained on adaptive runs at L=32,64, R=20000" % n_seeds,
+        "plain": {"steps": 400, "error_per_spin": stats(plain)},
+        "adaptive": {"alpha": 0.85, "steps": stats(sa),
+                     "error_per_spin": stats([r["error_adaptive"] for r in res])},
+        "learned": {"alpha_min": 0.80, "steps": stats(sl),
+                    "error_per_spin": stats([r["error_learned"] for r in res]),
+                    "accepted": float(np.mean([r["accepted"] for r in res])),
+                    "alpha_mean": float(np.mean([r["alpha_mean_learned"] for r in res]))},
+        "steps_ratio_learned_to_adaptive": float(np.mean(sl) / np.mean(sa)),
+        "training": {"rows": int(X.shape[0]), "loss_first": losses[0], "loss_last": losses[-1],
+                     "seconds": t_train,
+                     "mean_step_factor": float(np.mean([i["mean_step_factor"] for i in info]))},
+        "seconds": time.perf_counter() - t0}
 
 
 def cpu_baseline(betas, energies):
@@ -241,6 +296,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layouts", default="msc64,int8")
     ap.add_argument("--headline-only", action="store_true")
+    ap.add_argument("--no-schedules", action="store_true",
+                    help="skip the plain / adaptive / learned schedule comparison")
     ap.add_argument("--update", choices=("metropolis", "heatbath"), default="metropolis",
                     help="spin update of the layout runs (profiling the heatbath sweep)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -296,7 +353,11 @@ def main():
             "resample_copy_bytes": copy_bytes,
             "copy_us_per_step": copy_ms * 1e3,
             "copy_hbm_gbs": copy_bytes / (copy_ms * 1e-3) / 1e9,
-            "beta_f_error_per_spin": {"at_last_step": err[-1], "max": max(err)},
+            "beta_f_error_per_spin": {
+                "beta": prof["final"]["beta"],
+                "value": abs(prof["final"]["minus_beta_F"] - lnz[N_STEPS]) / (L * L),
+                "jackknife_sigma": math.sqrt(prof["final"]["jk_var_beta_F"]) / (L * L),
+                "timed_steps_max": max(err)},
             "beta_last": recs[-1]["beta"],
             "blocking_last": {k: recs[-1][k] for k in ("r_eff_E", "r_eff_absM", "err_e")},
             "sweep_geometry": prof["geometry"],
@@ -348,13 +409,13 @@ def main():
                                                           resample=rule)
             n = prof["steps"]
             sizes = np.array([r["R_i"] for r in recs[1:]], dtype=np.float64)
-            err = abs(recs[-1]["minus_beta_F"] - lnz[K]) / (L * L)
+            err = abs(prof["final"]["minus_beta_F"] - lnz[N_STEPS]) / (L * L)
             extra["l64_%s_msc64" % rule] = {
                 "attempts_per_ns": attempts / wall / 1e9, "ms_per_step": wall * 1e3 / K,
                 "resample_us_per_step": prof["ms_resample"] / n * 1e3,
                 "copy_us_per_step": prof["ms_copy"] / n * 1e3,
                 "R_i_mean": float(sizes.mean()), "R_i_std": float(sizes.std()),
-                "beta_f_error_per_spin_at_last_step": err}
+                "beta_f_error_per_spin_at_beta_c": err}
             run.close()
             torch.cuda.empty_cache()
         log("timing L=64, R=100000, multinomial, heatbath, multispin: %d steps" % K)
@@ -370,7 +431,7 @@ def main():
             "sweep_ms_per_step": sweep_ms, "philox_calls_per_word": calls / words if words else 0.0,
             "sweep_alu_tops": alg / (sweep_ms * 1e-3) / 1e12,
             "sweep_alu_frac": alg / (sweep_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
-            "beta_f_error_per_spin_at_last_step": abs(recs[-1]["minus_beta_F"] - lnz[K]) / (L * L)}
+            "beta_f_error_per_spin_at_beta_c": abs(prof["final"]["minus_beta_F"] - lnz[N_STEPS]) / (L * L)}
         run.close()
         torch.cuda.empty_cache()
         log("timing the 64-run batch: 200 steps")
@@ -379,6 +440,10 @@ def main():
         log("timing the combination of 64 independent runs (L=32, R=2000, nearest): 200 steps")
         extra["runs_combined"] = time_weighted(pa, torch)
         torch.cuda.empty_cache()
+        if not args.no_schedules:
+            log("plain, adaptive and learned schedules at L=128, R=100000, 16 seeds")
+            extra["schedules_compared"] = compare_schedules(pa, torch)
+            torch.cuda.empty_cache()
 
     head_layout = "msc64" if "msc64" in results else list(results)[0]
     head = results[head_layout]
@@ -401,6 +466,7 @@ def main():
                    "L": L, "R": R, "theta": THETA, "n_steps": N_STEPS, "seed": SEED,
                    "steps_timed": "1..%d" % K},
         "resample_us_per_step": head["resample_us_per_step"],
+        "beta_f_error_per_spin": head["beta_f_error_per_spin"],
         "roofline": roof,
         "copy_roofline": copy_roof,
         "layouts": results,

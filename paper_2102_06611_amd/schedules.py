@@ -11,6 +11,24 @@ logged training rows between device tensors.
 * Learned: a 35 -> 64 -> 64 -> 1 perceptron proposes log(dbeta sigma_E) from
   the histogram features; a proposal is taken only if its overlap is at least
   alpha_min, otherwise the adaptive step is used.
+
+Training targets (error-budget steps).  In the small-step limit a step adds
+dbeta^2 sigma^2(E) / R_eff(E) to the variance of beta F (Sec. "Free-energy
+estimate", Eq. varF-tdlimit), so the allocation of steps that reaches a given
+total of these terms with the fewest steps has dbeta sigma_E / sqrt(R_eff)
+constant (from minimising sum_i 1 / dbeta_i at fixed sum_i dbeta_i^2 w_i over
+the beta range); with R_eff = R that is the constant-overlap schedule.  The
+variance of a whole run, measured by its single-run jackknife, is larger than
+this sum (the populations of successive steps are correlated), so a step
+schedule may spend a small fraction eps of that measured variance on larger
+steps.  For each adaptive training run (records i = 0..n, steps dbeta*_i):
+    w_i = sigma_E,i-1^2 / R_eff,i-1 (R_eff from the blocking analysis, at most
+          R_{i-1}, smoothed over 9 steps),
+    B = sum_i dbeta*_i^2 w_i + eps jk_var(beta F_n)      (the white variance budget),
+    dbeta_i = c / sqrt(w_i) with c = B / sum_i dbeta*_i sqrt(w_i)   (its optimum),
+and the target is y_i = log(dbeta_i sigma_E,i-1), capped at log(0.48): a
+Gaussian histogram has overlap 0.81 there, so proposals stay above the
+guard's alpha_min = 0.80.
 """
 from __future__ import annotations
 
@@ -60,8 +78,14 @@ def learned_run(params, L: int, R: int, theta: int, seed: int, alpha_min: float,
     return run
 
 
+EPS_BUDGET = 0.1   # share of the run's measured variance of beta F spent on larger steps
+Y_CAP = 0.48       # largest dbeta sigma_E of a target (Gaussian overlap 0.81)
+
+
 def training_rows(run: Run, device: str = "cuda:0"):
-    """(X [n, 35], t [n]) device tensors from a run's schedule log (NaN rows dropped)."""
+    """(X [n, 35], t [n]) device tensors from a run's schedule log (NaN rows
+    dropped): the features entering each step and log(dbeta* sigma_E) of the
+    adaptive step taken."""
     import torch
     n, _, _ = run.schedule_log()
     X = torch.zeros((max(n, 1), PA_MLP_IN), dtype=torch.float32, device=device)
@@ -69,6 +93,29 @@ def training_rows(run: Run, device: str = "cuda:0"):
     run.schedule_log(X, t)
     keep = torch.isfinite(t[:n])
     return X[:n][keep].contiguous(), t[:n][keep].contiguous()
+
+
+def budget_targets(run: Run, eps: float = EPS_BUDGET, cap: float = Y_CAP, window: int = 9):
+    """Error-budget targets y_i = log(dbeta_i sigma_E,i-1), i = 1..n, of an
+    adaptive run (see the module docstring), from its records."""
+    n, _ = run.current()
+    recs = [run.observables(i) for i in range(n + 1)]
+    beta = np.array([r["beta"] for r in recs])
+    Ri = np.array([r["R_i"] for r in recs], dtype=np.float64)
+    sE = np.array([r["sum_E"] for r in recs], dtype=np.float64)
+    sE2 = np.array([r["sum_E2"] for r in recs], dtype=np.float64)
+    var = np.maximum(sE2 / Ri - (sE / Ri) ** 2, 0.0)[:-1]
+    reff = np.array([r["r_eff_E"] for r in recs])[:-1]
+    reff = np.where(np.isfinite(reff), np.minimum(reff, Ri[:-1]), Ri[:-1])
+    w = var / np.maximum(reff, 1.0)
+    k = np.ones(window) / window  # moving average (edges: the mean of what is there)
+    w = np.convolve(w, k, mode="same") / np.convolve(np.ones_like(w), k, mode="same")
+    db = np.diff(beta)
+    B = float(np.sum(db * db * w)) + eps * recs[n]["jk_var_beta_F"]
+    c = B / float(np.sum(db * np.sqrt(w)))
+    y = np.log(np.minimum(c * np.sqrt(var / w), cap))
+    return y, {"V_white": float(np.sum(db * db * w)), "V_jackknife": recs[n]["jk_var_beta_F"],
+               "mean_step_factor": float(np.mean(np.exp(y) / (db * np.sqrt(var))))}
 
 
 def init_params(seed: int, device: str = "cuda:0"):
@@ -102,16 +149,25 @@ def train(X, t, iters: int = 3000, lr: float = 3e-3, seed: int = 0,
 
 
 def collect(Ls, R: int, seeds, theta: int, alpha: float, beta_final: float, max_steps: int = 4000,
-            stream=None):
-    """Training rows from adaptive runs: one row per temperature step."""
+            stream=None, targets: str = "budget", info=None):
+    """Training rows from adaptive runs: one row per temperature step but the
+    last (which stops at beta_final).  targets = "budget": the error-budget
+    steps; "adaptive": the adaptive step itself, log(dbeta* sigma_E)."""
     import torch
     Xs, ts = [], []
     for L in Ls:
         for s in seeds:
             run = adaptive_run(L, R, theta, s, alpha, beta_final, max_steps, stream=stream)
+            n, _ = run.current()
             X, t = training_rows(run)
-            Xs.append(X)
-            ts.append(t)
+            assert X.shape[0] == n, "an adaptive run logs every step"
+            if targets == "budget":
+                y, meta = budget_targets(run)
+                t = torch.tensor(y, dtype=torch.float32, device=X.device)
+                if info is not None:
+                    info.append(dict(L=L, seed=s, steps=n, **meta))
+            Xs.append(X[:-1])
+            ts.append(t[:-1])
             run.close()
     return torch.cat(Xs).contiguous(), torch.cat(ts).contiguous()
 
@@ -150,13 +206,12 @@ def main(argv=None):
     """
     import argparse
     import json
-    import os
     import time
     import torch
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="smaller lattices and populations")
-    ap.add_argument("--ln-z", type=float, default=None,
-                    help="exact ln Z at beta_final for the evaluation lattice")
+    ap.add_argument("--ln-z", type=float, required=True,
+                    help="exact ln Z at beta_final = 1 for the evaluation lattice")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     t0 = time.time()
@@ -167,10 +222,6 @@ def main(argv=None):
     X, t = collect(train_L, train_R, range(500, 506), 10, 0.85, 1.0)
     params, losses = train(X, t, iters=4000, lr=2e-3)
     ln_z = args.ln_z
-    if ln_z is None:
-        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-        pts = json.load(open(os.path.join(root, "tests", "golden", "exact_lnz.json")))["points"]
-        ln_z = pts["L%d_1" % eval_L]
     res = compare(params, eval_L, eval_R, 10, [900 + s for s in seeds], ln_z)
     print(json.dumps({"train": {"L": list(train_L), "R": train_R, "rows": int(X.shape[0]),
                                 "loss_first": losses[0], "loss_last": losses[-1]},

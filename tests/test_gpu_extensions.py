@@ -435,26 +435,30 @@ def test_autotuner_times_candidates_and_keeps_results():
 
 
 def test_learned_schedule_against_plain_adaptive():
-    """Trained on adaptive runs at L = 16 and 32, the learned schedule reaches
-    beta_f = 0.8 at L = 32 in as many steps as the adaptive one (both aim at
-    the same overlap, so the network replaces the bisection rather than
-    shortening the schedule), with its proposals passing the overlap guard,
-    the realised overlap on target, and a free-energy error of the same size
-    (both compared with Kaufman's ln Z)."""
+    """Trained on error-budget targets from adaptive runs at L = 16 and 32
+    (R = 5000), the learned schedule reaches beta_f = 0.8 at L = 32, R = 20000
+    in at most 0.9 times the adaptive schedule's steps, its proposals passing
+    the overlap guard, at a free-energy error (against Kaufman's ln Z, 16
+    seeds) no worse than the adaptive schedule's within two standard errors
+    and below 1e-4 per spin."""
     from oracle import exact
-    X, t = schedules.collect((16, 32), 5000, range(500, 504), 5, 0.85, 0.8)
+    info = []
+    X, t = schedules.collect((16, 32), 5000, range(500, 508), 5, 0.85, 0.8, info=info)
+    log(info)
     assert X.shape[0] > 100 and torch.isfinite(t).all()
-    params, losses = schedules.train(X, t, iters=1500, lr=3e-3)
+    params, losses = schedules.train(X, t, iters=2000, lr=3e-3)
     assert losses[-1] < 0.1 * losses[0]
     lnz = float(exact.ln_z_kaufman(32, 0.8))
-    res = schedules.compare(params, 32, 5000, 5, [900, 901, 902, 903], lnz, beta_final=0.8)
-    log(res)
-    sa = np.mean([r["steps_adaptive"] for r in res])
-    sl = np.mean([r["steps_learned"] for r in res])
-    assert sl <= 1.03 * sa
+    res = schedules.compare(params, 32, 20000, 5, list(range(900, 916)), lnz, beta_final=0.8)
+    sa = np.array([r["steps_adaptive"] for r in res], dtype=float)
+    sl = np.array([r["steps_learned"] for r in res], dtype=float)
+    ea = np.array([r["error_adaptive"] for r in res])
+    el = np.array([r["error_learned"] for r in res])
+    log("steps", sa.mean(), sl.mean(), "errors", ea.mean(), el.mean(),
+        "accepted", np.mean([r["accepted"] for r in res]))
+    assert sl.mean() <= 0.9 * sa.mean()
     assert np.mean([r["accepted"] for r in res]) > 0.9
-    assert abs(np.mean([r["alpha_mean_learned"] for r in res]) - 0.85) < 0.02
-    ea = np.mean([r["error_adaptive"] for r in res])
-    el = np.mean([r["error_learned"] for r in res])
-    assert ea < 2e-3 and el < 2e-3
-    assert el < 3 * ea + 2e-4
+    assert np.all([r["alpha_mean_learned"] >= 0.80 for r in res])
+    se = math.sqrt(ea.var(ddof=1) / len(ea) + el.var(ddof=1) / len(el))
+    assert el.mean() <= ea.mean() + 2 * se
+    assert ea.mean() < 1e-4 and el.mean() < 1e-4
