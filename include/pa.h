@@ -266,6 +266,9 @@ pa_status pa_batch_create(const pa_config *cfgs, int32_t n_runs, void *dev_works
                           size_t bytes, void *stream, pa_batch **out);
 pa_status pa_batch_run(pa_batch *b, int32_t n_steps);
 pa_status pa_batch_observables(pa_batch *b, int32_t run, int32_t step, pa_obs *out);
+/* As pa_get_population, for run `run` of the batch.  Synchronises. */
+pa_status pa_batch_get_population(pa_batch *b, int32_t run, int32_t first, int32_t count,
+                                  int8_t *spins, int32_t *fam, int32_t *E, int32_t *M);
 pa_status pa_batch_sync(pa_batch *b);
 pa_status pa_batch_set_sweep_launch(pa_batch *b, int32_t L, int32_t threads,
                                     int32_t groups_per_block, int32_t variant);

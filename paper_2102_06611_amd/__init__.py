@@ -108,6 +108,8 @@ SIGNATURES = {
     "pa_batch_create": (_i32, [_P(pa_config), _i32, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "pa_batch_run": (_i32, [_vp, _i32]),
     "pa_batch_observables": (_i32, [_vp, _i32, _i32, _P(pa_obs)]),
+    "pa_batch_get_population": (_i32, [_vp, _i32, _i32, _i32, _P(ctypes.c_int8), _P(_i32),
+                                       _P(_i32), _P(_i32)]),
     "pa_batch_weighted": (_i32, [_vp, _i32, _i32, _vp]),
     "pa_overlap_correlation": (_i32, [_vp, _i32, _vp]),
     "pa_batch_sync": (_i32, [_vp]),
@@ -370,6 +372,7 @@ class Batch:
             cfgs[k] = cfg
             self._keep.append(arr)
         self.n = len(specs)
+        self._L = [s["L"] for s in specs]
         nbytes = ctypes.c_size_t()
         _check(lib().pa_batch_workspace_size(cfgs, self.n, ctypes.byref(nbytes)))
         self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
@@ -400,6 +403,19 @@ class Batch:
         _check(lib().pa_batch_observables(self.h, int(run), int(step), ctypes.byref(o)), self.h,
                batch=True)
         return o.as_dict()
+
+    def population(self, run: int, first: int, count: int, spins: bool = True):
+        """(spins [count, N] int8, fam, E, M) of replicas [first, first + count) of run `run`."""
+        N = self._L[run] ** 2
+        s = np.zeros((count, N), dtype=np.int8) if spins else None
+        fam = np.zeros(count, dtype=np.int32)
+        E = np.zeros(count, dtype=np.int32)
+        M = np.zeros(count, dtype=np.int32)
+        _check(lib().pa_batch_get_population(
+            self.h, int(run), int(first), int(count),
+            s.ctypes.data_as(_P(ctypes.c_int8)) if spins else None, fam.ctypes.data_as(_P(_i32)),
+            E.ctypes.data_as(_P(_i32)), M.ctypes.data_as(_P(_i32))), self.h, batch=True)
+        return s, fam, E, M
 
     def weighted(self, first: int, count: int = 1) -> List[dict]:
         """The runs combined at steps first .. first + count - 1 (pa_batch_weighted)."""

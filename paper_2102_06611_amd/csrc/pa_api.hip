@@ -654,21 +654,20 @@ pa_status pa_copy_counts(pa_ctx *ctx, int32_t *cnt, int64_t cap, int64_t *n) {
     return PA_OK;
 }
 
-pa_status pa_get_population(pa_ctx *ctx, int32_t first, int32_t count, int8_t *spins,
-                            int32_t *fam, int32_t *E, int32_t *M) {
-    if (!ctx) return fail(nullptr, PA_ERR_ARG, "NULL handle");
-    pa_batch *B = &ctx->b;
+static pa_status engine_get_population(pa_batch *B, int r, int32_t first, int32_t count,
+                                       int8_t *spins, int32_t *fam, int32_t *E, int32_t *M) {
+    if (r < 0 || r >= B->n) return fail(B, PA_ERR_ARG, "run index outside the batch");
     RunState s;
-    pa_status e = read_state(B, 0, &s);
+    pa_status e = read_state(B, r, &s);
     if (e) return e;
-    const RunDesc &d = B->desc[0];
+    const RunDesc &d = B->desc[r];
     if (first < 0 || count < 0 || (int64_t)first + count > s.R_cur)
         return fail(B, PA_ERR_ARG, "replica range outside the population");
     if (count == 0) return PA_OK;
     if (spins) {
         std::vector<int8_t> tmp((size_t)64 * d.N);
         for (int g = first / 64; g <= (first + count - 1) / 64; ++g) {
-            PA_HIP(B, launch_unpack_group(B->lc, 0, g, d.N));
+            PA_HIP(B, launch_unpack_group(B->lc, r, g, d.N));
             PA_HIP(B, hipStreamSynchronize(B->stream));
             PA_HIP(B, hipMemcpy(tmp.data(), d.stage, tmp.size(), hipMemcpyDeviceToHost));
             int lo = std::max(first, g * 64), hi = std::min(first + count, g * 64 + 64);
@@ -680,6 +679,18 @@ pa_status pa_get_population(pa_ctx *ctx, int32_t first, int32_t count, int8_t *s
     if (E) PA_HIP(B, hipMemcpy(E, d.E + first, (size_t)count * 4, hipMemcpyDeviceToHost));
     if (M) PA_HIP(B, hipMemcpy(M, d.M + first, (size_t)count * 4, hipMemcpyDeviceToHost));
     return PA_OK;
+}
+
+pa_status pa_get_population(pa_ctx *ctx, int32_t first, int32_t count, int8_t *spins,
+                            int32_t *fam, int32_t *E, int32_t *M) {
+    if (!ctx) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    return engine_get_population(&ctx->b, 0, first, count, spins, fam, E, M);
+}
+
+pa_status pa_batch_get_population(pa_batch *b, int32_t run, int32_t first, int32_t count,
+                                  int8_t *spins, int32_t *fam, int32_t *E, int32_t *M) {
+    if (!b) return fail(nullptr, PA_ERR_ARG, "NULL handle");
+    return engine_get_population(b, run, first, count, spins, fam, E, M);
 }
 
 pa_status pa_set_population(pa_ctx *ctx, int32_t step, int32_t R_i, const int8_t *spins,

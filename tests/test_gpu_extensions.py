@@ -462,3 +462,78 @@ def test_learned_schedule_against_plain_adaptive():
     se = math.sqrt(ea.var(ddof=1) / len(ea) + el.var(ddof=1) / len(el))
     assert el.mean() <= ea.mean() + 2 * se
     assert ea.mean() < 1e-4 and el.mean() < 1e-4
+
+
+def _tail_decay_length(cq):
+    """tau_R of the exponential tail C_q(d) ~ exp(-d / tau_R) (Eq. exponential_R):
+    a least-squares line through ln C_q(d) from the first d where C_q has fallen
+    to 0.3 C_q(1) (past the faster initial decay) to the last d before it drops
+    below 0.03 (far above the noise of the average, about 0.002)."""
+    d_b = 1
+    while d_b + 1 < len(cq) and cq[d_b + 1] >= 0.03:
+        d_b += 1
+    d_a = next(d for d in range(1, len(cq)) if cq[d] <= 0.3 * cq[1] or d >= d_b - 1)
+    d_a = min(d_a, d_b - 1)
+    d = np.arange(d_a, d_b + 1)
+    slope = np.polyfit(d, np.log(cq[d_a:d_b + 1]), 1)[0]
+    return -1.0 / slope
+
+
+def test_overlap_correlation_tail_matches_the_paper():
+    """Sec. "Effective population size" (Fig. correlation_function, Eq.
+    exponential_R): L = 16, R = 50000 near beta_c = 0.44, theta = 1, 5, 10 give
+    tau_R = 32.3, 3.0, 1.8.  The step size is not stated there; Delta beta = 0.01
+    (44 steps), the paper's usual step at these sizes, is taken.  The paper's
+    runs use sequential Metropolis updates and these checkerboard ones (a
+    reading of the update order), so each tau_R is required within 50 %, and
+    the order theta = 1 > 5 > 10."""
+    betas = linear_schedule(0.44, 44)
+    taus = {}
+    for theta in (1, 5, 10):
+        cqs = []
+        for seed in range(4):
+            r = pa.Run(16, 50000, betas, theta, 300 + seed, "nearest", "msc64")
+            r.run(44)
+            cqs.append(r.overlap_correlation(256))
+            r.close()
+        taus[theta] = _tail_decay_length(np.mean(cqs, axis=0))
+    log("tau_R", taus)
+    assert taus[1] > taus[5] > taus[10]
+    for theta, want in ((1, 32.3), (5, 3.0), (10, 1.8)):
+        assert 0.5 * want <= taus[theta] <= 1.5 * want, (theta, taus[theta], want)
+
+
+def test_full_size_covering_design_members_match_single_runs():
+    """The 64-run covering design at full size (L in {16, 32, 64, 128} x R in
+    {1000, 5000, 20000, 50000}, beta 0 -> 0.4407 in 200 steps, theta = 10), run
+    60 steps in one batch: the members L = 128 / R = 50000 and L = 16 / R = 1000
+    (and one with L = 32 and one with L = 64) equal single runs record by
+    record, and on sampled replica groups spin by spin."""
+    from workloads import batched_design
+    design = batched_design(64)
+    specs = [dict(L=d.L, R=d.R, theta=d.theta, seed=d.seed, resample=d.resample,
+                  layout=d.layout, betas=d.betas()) for d in design]
+    b = pa.Batch(specs, stream=torch.cuda.Stream())
+    k = 60
+    b.run(k)
+    b.sync()
+    members = [m for m, d in enumerate(design) if (d.L, d.R) in ((128, 50000), (16, 1000))][:2]
+    members += [m for m, d in enumerate(design) if (d.L, d.R) in ((32, 20000), (64, 5000))][:2]
+    rng = np.random.default_rng(5)
+    for m in members:
+        d = design[m]
+        log("member", m, d.L, d.R)
+        single = pa.Run(d.L, d.R, d.betas(), d.theta, d.seed, d.resample, d.layout)
+        single.run(k)
+        for i in range(k + 1):
+            assert same_record(b.observables(m, i), single.observables(i)), (m, i)
+        _, R_i = single.current()
+        G = (R_i + 63) // 64
+        for g in sorted(set([0, G - 1] + list(rng.integers(0, G, 3)))):
+            lo, hi = 64 * g, min(64 * g + 64, R_i)
+            got = b.population(m, lo, hi - lo)
+            want = single.population(lo, hi - lo)
+            for x, y in zip(got, want):
+                assert np.array_equal(x, y), (m, g)
+        single.close()
+    b.close()
