@@ -435,6 +435,10 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         pa_status e = upload_class_map(B, (int)k);
         if (e) return e;
     }
+    lc.max_nblk = 1;  // multinomial runs (R < 2^23): at most 8192 blocks, 64 KiB of draw LDS
+    for (int r = 0; r < n; ++r)
+        if (cfgs[r].resample == PA_RESAMPLE_MULTINOMIAL)
+            lc.max_nblk = std::max(lc.max_nblk, B->lay.plans[r].nblk);
     lc.any_nearest = lc.any_multi = lc.any_poisson = false;
     lc.any_msc = lc.any_int8 = false;
     lc.any_update[0] = lc.any_update[1] = false;
@@ -811,6 +815,7 @@ pa_status pa_set_state(pa_ctx *ctx, const void *buf, size_t len) {
     s.lnq_hi = s.lnq_lo = 0.0;
     s.w_total = 0;
     s.sum_cnt2 = 0;
+    s.reduce_done = 0;
     // family labels, energies and magnetisations are checked before anything
     // reaches the device (the energies index the histogram there): labels are
     // beta_0 replica indices in tree order (non-decreasing), E in [-2N, 2N] with

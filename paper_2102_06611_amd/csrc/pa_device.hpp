@@ -56,6 +56,8 @@ struct RunState {
     unsigned long long philox_calls;  // Philox calls counted by the sweeps (profiling)
     unsigned long long sweep_words;   // 64-replica words updated by the sweeps
     double s_hi, s_lo;                // S = sum_l n_l w_l of the step in progress (Eq. Q)
+    int32_t kmin_step;                // level origin of wlev / zlev of the step in progress
+    int32_t reduce_done;              // k_reduce blocks finished in the step (0 between steps)
     // free-energy jackknife: for block k of the n_F = min(kBlocks, R) blocks,
     // sum over the steps so far of ln Q^(k) - ln Q (Q without block k of the
     // parents, Eq. Q), so that sample k of -beta F is -beta F + jk_F[k]

@@ -36,6 +36,7 @@ struct LaunchCtx {
     bool any_msc, any_int8;  // layouts present in the batch
     bool any_update[2];      // spin-update rules present in the batch (PA_UPDATE_*)
     bool count_calls = false;  // sweeps count the Philox calls the words need (pa_profile 3)
+    int max_nblk = 1;          // most slot blocks of a multinomial run (LDS of its draws)
 };
 
 void set_last_error(const char *msg);  // for pa_last_error(NULL)

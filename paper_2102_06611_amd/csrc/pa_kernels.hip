@@ -10,8 +10,9 @@
 //   k_offsets      exclusive prefix sum of r_j (tree order of the children), R_i
 //   k_gather_*     children <- parents: spins and family labels
 //   k_sweep        theta checkerboard Metropolis sweeps in LDS + E, M
-//   k_reduce       population sums, family statistics, next energy histogram
-//   k_record       record i; the new population becomes current
+//   k_reduce       population sums, family statistics, next energy histogram;
+//                  its last block writes record i and makes the new population current
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -265,20 +266,19 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
         if (n) part = dd_add(part, dd_mul_d(w, (double)n));
         if (!exact) w = dd_mul(w, stride);
     }
-    sh_hi[threadIdx.x] = part.hi;
-    sh_lo[threadIdx.x] = part.lo;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            dd a{sh_hi[threadIdx.x], sh_lo[threadIdx.x]};
-            dd b{sh_hi[threadIdx.x + s], sh_lo[threadIdx.x + s]};
-            dd c = dd_add(a, b);
-            sh_hi[threadIdx.x] = c.hi;
-            sh_lo[threadIdx.x] = c.lo;
-        }
-        __syncthreads();
+    // S: a butterfly within each wavefront (the double-double sum is
+    // commutative, so every lane ends with the same value), then the four
+    // wavefronts' sums in a fixed order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        part = dd_add(part, dd{__shfl_xor(part.hi, o, 64), __shfl_xor(part.lo, o, 64)});
+    if ((threadIdx.x & 63) == 0) {
+        sh_hi[threadIdx.x >> 6] = part.hi;
+        sh_lo[threadIdx.x >> 6] = part.lo;
     }
-    const dd S{sh_hi[0], sh_lo[0]};
+    __syncthreads();
+    const dd S = dd_add(dd_add(dd{sh_hi[0], sh_lo[0]}, dd{sh_hi[1], sh_lo[1]}),
+                        dd_add(dd{sh_hi[2], sh_lo[2]}, dd{sh_hi[3], sh_lo[3]}));
     if (threadIdx.x == last) {
         const double e_min = -2.0 * rd.N + 4.0 * kmin;
         dd lnq;
@@ -292,6 +292,7 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
         st->lnq_lo = lnq.lo;
         st->s_hi = S.hi;
         st->s_lo = S.lo;
+        st->kmin_step = kmin;  // k_offsets resets st->kmin while its jackknife blocks run
     }
     bool amb = false;
     const double R2_32 = ldexp((double)rd.R, 32);
@@ -350,17 +351,16 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
 // of every Q.  Block k of the population entering step i is the slot range
 // [floor(k R_{i-1} / n_F), floor((k + 1) R_{i-1} / n_F)) of the tree-ordered
 // population, n_F = min(kBlocks, R) for the whole run.  One workgroup per
-// (run, block) sums the parents' weights w = e^{-dbeta (E - E_min)} of its
-// block (the level weights of k_norm) in a fixed order; k_record turns the
-// sums into ln Q^(k) - ln Q = ln(1 - W_k / S) - ln(1 - B_k / R_{i-1}).
-__global__ void __launch_bounds__(256) k_jack_weights(const RunDesc *runs) {
-    const RunDesc &rd = runs[blockIdx.x / kBlocks];
-    const int k = blockIdx.x % kBlocks;
+// (run, block) -- extra blocks of the k_offsets launch -- sums the parents'
+// weights w = e^{-dbeta (E - E_min)} of its block (the level weights of
+// k_norm) in a fixed order; the record turns the sums into ln Q^(k) - ln Q =
+// ln(1 - W_k / S) - ln(1 - B_k / R_{i-1}).
+__device__ void jack_weights(const RunDesc &rd, int k) {
     RunState *st = rd.st;
     const int nF = min(kBlocks, rd.R);
     if (st->err || k >= nF) return;
     __shared__ double shd[16];
-    const int Rp = st->R_cur, kmin = st->kmin;
+    const int Rp = st->R_cur, kmin = st->kmin_step;
     const int lo = (int)((int64_t)k * Rp / nF), hi = (int)((int64_t)(k + 1) * Rp / nF);
     double s = 0.0;
     for (int j = lo + (int)threadIdx.x; j < hi; j += blockDim.x) {
@@ -521,8 +521,10 @@ __global__ void __launch_bounds__(256) k_counts_poisson(const RunDesc *runs, Wor
     }
 }
 
-// Multinomial, pass 1: quantised weight q_j of each parent (into cum[j]),
-// zeroed counts, block sums of q (part[b*8 + 3]).
+// Multinomial, pass 1: quantised weight q_j of each parent, its inclusive
+// prefix within the block of kSlotBlock parents (cum[j]), the block's total
+// (part[b*8 + 3]), zeroed counts and a zeroed per-block count (part[b*8 + 0],
+// which the draws increment).
 __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
@@ -530,129 +532,140 @@ __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, Work
     if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
     __shared__ int64_t sh[32];
     const int Rp = st->R_cur, kmin = st->kmin;
-    int64_t s = 0;
-    for (int j = b * kSlotBlock + (int)threadIdx.x; j < min((b + 1) * kSlotBlock, Rp);
-         j += blockDim.x) {
-        const uint64_t q = rd.zlev[((rd.E[j] + 2 * rd.N) >> 2) - kmin];
-        rd.cum[j] = q;
-        rd.cnt[j] = 0;
-        s += (int64_t)q;
-    }
-    const int64_t bs = block_sum_i64(s, sh);
-    if (threadIdx.x == 0) rd.part[b * 8 + 3] = bs;
-}
-
-// Multinomial, pass 2: inclusive prefix of q_j -> cum[j]; block 0 records the
-// total quantised weight W.
-__global__ void __launch_bounds__(256) k_multi_cum(const RunDesc *runs, WorkMap map) {
-    int b;
-    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
-    RunState *st = rd.st;
-    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
-    __shared__ int64_t sh[32];
-    const int Rp = st->R_cur;
-    // the weights of the blocks before this one, and of all blocks, in one pass
-    int64_t v[2] = {0, 0};
-    for (int k = threadIdx.x; k < rd.nblk; k += blockDim.x) {
-        const int64_t q = rd.part[k * 8 + 3];
-        v[0] += k < b ? q : 0;
-        v[1] += q;
-    }
-    block_sum_i64v(v, sh);
-    __shared__ uint64_t base_sh;
-    if (threadIdx.x == 0) {
-        base_sh = (uint64_t)v[0];
-        if (b == 0) st->w_total = (uint64_t)v[1];
-    }
-    __syncthreads();
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
     uint64_t q[4] = {0, 0, 0, 0};
-    for (int m = 0; m < 4; ++m)
-        if (j + m < Rp) q[m] = rd.cum[j + m];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (j + m < Rp) {
+            q[m] = rd.zlev[((rd.E[j + m] + 2 * rd.N) >> 2) - kmin];
+            rd.cnt[j + m] = 0;
+        }
+    }
     int64_t tot;
-    uint64_t run = base_sh + (uint64_t)block_exclusive_scan((int64_t)(q[0] + q[1] + q[2] + q[3]), sh, &tot);
+    uint64_t run = (uint64_t)block_exclusive_scan((int64_t)(q[0] + q[1] + q[2] + q[3]), sh, &tot);
+#pragma unroll
     for (int m = 0; m < 4; ++m) {
         run += q[m];
         if (j + m < Rp) rd.cum[j + m] = run;
     }
+    if (threadIdx.x == 0) {
+        rd.part[b * 8 + 3] = tot;
+        rd.part[b * 8 + 0] = 0;
+    }
 }
 
-// Multinomial, pass 3: draw d (of R) picks the first parent with
-// cum > floor(U64_d * W / 2^64); counts accumulate atomically (order-free).
-// The search first runs over every 64th cumulative weight, held in LDS, and
-// then over the at most 64 parents of the chosen stretch.  Four blocks share
-// each slot block's 1024 draws (one draw per thread).
-constexpr int kCoarse = 4096;
-constexpr int kDrawSplit = kSlotBlock / 256;  // one draw per thread (two or four were slower)
+// Multinomial, pass 2: draw d (of R) picks the first parent whose global
+// cumulative weight exceeds floor(U64_d * W / 2^64).  Every block first forms
+// the exclusive prefix of the parent blocks' totals in LDS (the block bases;
+// W is their sum), finds a draw's parent block there, and then the parent
+// inside the block from the in-block prefix: sixteen stretches of 64, their
+// eighths, then single parents, each level by independent loads.  Counts
+// accumulate atomically (order-free); so does each parent block's count of
+// children (part[b*8 + 0], for k_offsets), gathered in LDS first so that a
+// block adds each parent block's share once.  A block of kSlotBlock threads
+// makes the kSlotBlock draws of one slot block (one draw per thread), so that
+// the LDS index and the shares are built and added once per 1024 draws.
 
-__global__ void __launch_bounds__(256) k_multi_draw(const RunDesc *runs, WorkMap map) {
-    int b;
-    const RunDesc &rd = runs[map_block(map, blockIdx.x / kDrawSplit, &b)];
-    RunState *st = rd.st;
-    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
-    __shared__ uint64_t coarse[kCoarse];
-    const int Rp = st->R_cur, i = st->step + 1;
-    const uint64_t W = st->w_total;
-    const int nc = (Rp + 63) >> 6;  // stretch k covers parents [64k, 64k + 63]
-    const bool use_coarse = nc <= kCoarse;
-    const gptr<const uint64_t> cum = global(static_cast<const uint64_t *>(rd.cum));
-    if (use_coarse) {
-#pragma unroll 8
-        for (int k = threadIdx.x; k < nc; k += blockDim.x) coarse[k] = cum[min(64 * k + 63, Rp - 1)];
-    }
-    __syncthreads();
-    const int d = b * kSlotBlock + (int)(blockIdx.x % kDrawSplit) * 256 + (int)threadIdx.x;
-    if (d >= rd.R) return;
+// One multinomial draw d: its uniform, the stretch of 64 parents that holds
+// its target (from the LDS index of every 64th global cumulative weight, or,
+// for populations too large for that index, from the LDS block bases and the
+// ends of the block's sixteen stretches), then the eighth and the parent by
+// independent loads of the in-block prefix; its count and the block's LDS
+// count are incremented.
+__device__ __forceinline__ void draw_one(const RunDesc &rd, int d, int i, uint64_t W,
+                                         const uint64_t *base, const uint64_t *coarse, int nc,
+                                         int nbp, int Rp, int32_t *bcnt) {
     const U4 x = philox(rd.key0, rd.key1, (uint32_t)(d >> 1), (uint32_t)i, 0u, kTagMulti);
     const uint64_t U = (d & 1) ? ((uint64_t)x.w << 32) | x.z : ((uint64_t)x.y << 32) | x.x;
     const uint64_t target = mulhi64(U, W);
-    int lo = 0, hi = Rp - 1;  // first j with cum[j] > target
-    if (use_coarse) {
-        int cl = 0, ch = nc - 1;  // first stretch whose last weight exceeds target
-        while (cl < ch) {
-            const int mid = (cl + ch) >> 1;
-            if (coarse[mid] > target) ch = mid; else cl = mid + 1;
+    const gptr<const uint64_t> cum = global(static_cast<const uint64_t *>(rd.cum));
+    int s0, pb;
+    if (coarse) {  // the first stretch whose last global cumulative weight exceeds target
+        int lo = 0, hi = nc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (coarse[mid] > target) hi = mid; else lo = mid + 1;
         }
-        // within the stretch (its last weight exceeds target): the eighths, then
-        // the parents of one eighth, each by eight independent loads
-        const int s0 = 64 * cl, last = min(64 * cl + 63, Rp - 1);
-        int e = 0;  // eighths whose last weight is <= target
+        s0 = 64 * lo;
+        pb = s0 / kSlotBlock;
+    } else {
+        int lo = 0, hi = nbp - 1;  // the last block whose base is <= target
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (base[mid] <= target) lo = mid; else hi = mid - 1;
+        }
+        pb = lo;
+        const uint64_t t = target - base[pb];
+        const int j0 = pb * kSlotBlock, lastb = min(j0 + kSlotBlock, Rp) - 1;
+        int e = 0;  // stretches of 64 whose last prefix is <= t
 #pragma unroll
-        for (int k = 0; k < 7; ++k) e += cum[min(s0 + 8 * k + 7, last)] <= target ? 1 : 0;
-        const int b0 = s0 + 8 * e;
-        int f = 0;
+        for (int k = 0; k < 15; ++k) e += cum[min(j0 + 64 * k + 63, lastb)] <= t ? 1 : 0;
+        s0 = j0 + 64 * e;
+    }
+    const uint64_t t = target - base[pb];  // below the block's total
+    const int last = min(pb * kSlotBlock + kSlotBlock, Rp) - 1;
+    int e2 = 0;  // eighths of the stretch
 #pragma unroll
-        for (int k = 0; k < 7; ++k) f += cum[min(b0 + k, last)] <= target ? 1 : 0;
-        lo = hi = b0 + f;
-    }
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cum[mid] > target) hi = mid; else lo = mid + 1;
-    }
-    atomicAdd(&rd.cnt[lo], 1);
+    for (int k = 0; k < 7; ++k) e2 += cum[min(s0 + 8 * k + 7, last)] <= t ? 1 : 0;
+    const int b0 = s0 + 8 * e2;
+    int f = 0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) f += cum[min(b0 + k, last)] <= t ? 1 : 0;
+    atomicAdd(&rd.cnt[b0 + f], 1);
+    atomicAdd(&bcnt[pb], 1);
 }
 
-// Multinomial, pass 4: block partials of the counts (as k_counts_nearest).
-__global__ void __launch_bounds__(256) k_count_partials(const RunDesc *runs, WorkMap map) {
+// LDS of the draws: block bases (8 bytes per parent block), their counts (4
+// bytes) and, while the population has at most kCoarse stretches of 64, the
+// index of every 64th global cumulative weight (8 bytes per stretch).
+constexpr int kCoarse = 4096;
+// the most any run with at most max_nblk parent blocks uses: 12 bytes per block,
+// plus 8 per stretch for runs of at most kCoarse / 16 blocks
+inline size_t draw_lds_bytes(int max_nblk) {
+    const size_t small = (size_t)std::min(max_nblk, kCoarse / (kSlotBlock / 64));
+    return std::max((size_t)max_nblk * 12, small * (12 + 8 * (kSlotBlock / 64)));
+}
+
+__global__ void __launch_bounds__(kSlotBlock) k_multi_draw(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
     if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    extern __shared__ uint64_t base[];  // [nbp] bases, [nc] coarse index if used, [nbp] int32 counts
     __shared__ int64_t sh[32];
-    const int Rp = st->R_cur;
-    int64_t s = 0, s2 = 0;
-    for (int j = b * kSlotBlock + (int)threadIdx.x; j < min((b + 1) * kSlotBlock, Rp);
-         j += blockDim.x) {
-        const int64_t c = rd.cnt[j];
-        s += c;
-        s2 += c * c;
+    const int Rp = st->R_cur, i = st->step + 1;
+    const int nbp = (Rp + kSlotBlock - 1) / kSlotBlock;
+    const int nc = (Rp + 63) >> 6;
+    uint64_t *coarse = nc <= kCoarse ? base + nbp : nullptr;
+    int32_t *bcnt = reinterpret_cast<int32_t *>(base + nbp + (coarse ? nc : 0));
+    const int per = (nbp + (int)blockDim.x - 1) / (int)blockDim.x;  // blocks per thread
+    const int kb = (int)threadIdx.x * per, ke = min(kb + per, nbp);
+    uint64_t s = 0;
+    for (int k = kb; k < ke; ++k) s += (uint64_t)rd.part[k * 8 + 3];
+    int64_t total;
+    uint64_t acc = (uint64_t)block_exclusive_scan((int64_t)s, sh, &total);
+    for (int k = kb; k < ke; ++k) {
+        base[k] = acc;
+        bcnt[k] = 0;
+        acc += (uint64_t)rd.part[k * 8 + 3];
     }
-    int64_t v[2] = {s, s2};
-    block_sum_i64v(v, sh);
-    if (threadIdx.x == 0) {
-        rd.part[b * 8 + 0] = v[0];
-        rd.part[b * 8 + 1] = v[1];
+    __syncthreads();
+    if (coarse) {
+        const gptr<const uint64_t> cum = global(static_cast<const uint64_t *>(rd.cum));
+#pragma unroll 8
+        for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+            const int j = min(64 * k + 63, Rp - 1);
+            coarse[k] = base[j / kSlotBlock] + cum[j];
+        }
+        __syncthreads();
     }
+    const uint64_t W = (uint64_t)total;
+    const int d = b * kSlotBlock + (int)threadIdx.x;
+    if (d < rd.R) draw_one(rd, d, i, W, base, coarse, nc, nbp, Rp, bcnt);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nbp; k += blockDim.x)
+        if (bcnt[k]) atomicAdd(reinterpret_cast<unsigned long long *>(&rd.part[k * 8 + 0]),
+                               (unsigned long long)bcnt[k]);
 }
 
 // off[j] = sum_{l<j} r_l (children of parent j occupy [off[j], off[j] + r_j)),
@@ -660,7 +673,12 @@ __global__ void __launch_bounds__(256) k_count_partials(const RunDesc *runs, Wor
 // PA_ERR_EXTINCT) and
 // sum r_j^2.  The histogram, consumed by k_norm, is cleared here so that the
 // reduction at the end of the step can build the next one.
-__global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap map) {
+__global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap map, int slot_blocks) {
+    if ((int)blockIdx.x >= slot_blocks) {  // the free-energy jackknife's weight sums
+        const int q = (int)blockIdx.x - slot_blocks;
+        jack_weights(runs[q / kBlocks], q % kBlocks);
+        return;
+    }
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
@@ -673,25 +691,28 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
     int c[4] = {0, 0, 0, 0};
     for (int m = 0; m < 4; ++m)
         if (j + m < Rp) c[m] = rd.cnt[j + m];
-    // children of the blocks before this one; all children and sum r_j^2 (one pass)
-    int64_t v[3] = {0, 0, 0};
+    // children of the blocks before this one and of all blocks (one pass); the
+    // block's sum of r_j^2 goes to the step's total
+    int64_t v[3] = {0, 0, (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2] +
+                              (int64_t)c[3] * c[3]};
     for (int k = threadIdx.x; k < rd.nblk; k += blockDim.x) {
         const int64_t r = rd.part[k * 8 + 0];
         v[0] += k < b ? r : 0;
         v[1] += r;
-        v[2] += rd.part[k * 8 + 1];
     }
     block_sum_i64v(v, sh);
-    if (threadIdx.x == 0) base_sh = v[0];
+    if (threadIdx.x == 0) {
+        base_sh = v[0];
+        if (v[2]) atomicAdd(reinterpret_cast<unsigned long long *>(&st->sum_cnt2), (unsigned long long)v[2]);
+    }
     if (b == 0) {
-        const int64_t total = v[1], sq = v[2];
+        const int64_t total = v[1];
         if (threadIdx.x == 0) {
             if (total > rd.C || total == 0) {
                 st->err = total ? PA_ERR_CAPACITY : PA_ERR_EXTINCT;
                 st->err_step = st->step + 1;
             } else {
                 st->R_new = (int32_t)total;
-                st->sum_cnt2 = sq;
                 rd.off[Rp] = (int32_t)total;
             }
             st->kmin = INT_MAX;
@@ -1912,10 +1933,12 @@ k_sweep(const RunDesc *runs, WorkMap map, int init, int gpb) {
 // block of kSlotBlock slots finds its runs (a block max-scan of the run starts)
 // and sums f, sum len^2 and sum len ln len over the runs that lie inside it;
 // a run that crosses the block's first or last slot is reported as a portion
-// (first_len / last_len with continuation flags) for k_record to stitch.  The
+// (first_len / last_len with continuation flags) for record_run to stitch.  The
 // block also adds its slots to the energy histogram that the next step's
 // k_norm reads.  Partials go to part[b*8 + k] (k = 0..7) and partd[b*2].
 constexpr int64_t kRunContPrev = 1ll << 32, kRunContNext = 1ll << 33, kRunSingle = 1ll << 34;
+
+__device__ void record_run(const RunDesc &rd);
 
 __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map) {
     int b;
@@ -2049,15 +2072,27 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     for (int k = threadIdx.x; k < 4 * (kb1 - kb0 + 1); k += blockDim.x)
         if (bsum[k]) atomicAdd(reinterpret_cast<unsigned long long *>(&rd.blk[4 * kb0 + k]), (unsigned long long)bsum[k]);
     block_histogram(rd, st, lev);
+    // the run's last block to finish writes the record: every block publishes
+    // its partials (release fence) before it counts itself done, and the last
+    // one reads them all after an acquire fence
+    __shared__ int last_sh;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last_sh = atomicAdd(&st->reduce_done, 1) == rd.nblk - 1;
+    }
+    __syncthreads();
+    if (!last_sh) return;
+    __threadfence();
+    record_run(rd);
+    if (threadIdx.x == 0) st->reduce_done = 0;
 }
 
-// One block per run: combine the partials of k_reduce, write record i (Sec.
-// "Model and observables" with N -> R_i; Eqs. rhot, rhos, one-step-Reff) and
-// make the new population current.
-__global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
-    const RunDesc &rd = runs[blockIdx.x];
+// The last k_reduce block of a run: combine the partials of all its blocks,
+// write record i (Sec. "Model and observables" with N -> R_i; Eqs. rhot, rhos,
+// one-step-Reff) and make the new population current.
+__device__ void record_run(const RunDesc &rd) {
     RunState *st = rd.st;
-    if (st->err) return;
     __shared__ int64_t sh[16 * 6];
     __shared__ double shd[32];
     const int Rn = st->R_new, nb = st->cur ^ 1;
@@ -2138,10 +2173,14 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
     }
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) tot_sh[q] = T[q];
+    // mean of the D_k (fixed-order block sum, broadcast through LDS)
+    __shared__ double dbar_sh;
+    {
+        const double t = block_sum_f64((int)threadIdx.x < nF ? dF[threadIdx.x] : 0.0, shd);
+        if (threadIdx.x == 0) dbar_sh = t / nF;
+    }
     __syncthreads();
-    double Dbar = 0.0;  // mean of the D_k, in block order (every thread)
-    for (int k = 0; k < nF; ++k) Dbar += dF[k];
-    Dbar /= nF;
+    const double Dbar = dbar_sh;
     const double Rd = (double)Rn;
     const double whole[4] = {
         (double)tot_sh[0] / Rd, (double)tot_sh[2] / Rd,
@@ -2181,11 +2220,19 @@ __global__ void __launch_bounds__(256) k_record(const RunDesc *runs) {
         bdev[threadIdx.x][14] = db * db;
     }
     __syncthreads();
-    if (threadIdx.x < 16) {  // sums over the blocks, each in block order
-        const int n = threadIdx.x == 14 ? nF : nbk;
+    {  // sums over the blocks: 16 strided partial sums per column, then their sum (fixed order)
+        __shared__ double cpart[16][16];
+        const int col = threadIdx.x & 15, part = threadIdx.x >> 4;
+        const int n = col == 14 ? nF : nbk;
         double t = 0.0;
-        for (int k = 0; k < n; ++k) t += bdev[k][threadIdx.x];
-        dsum[threadIdx.x] = t;
+        for (int k = part; k < n; k += 16) t += bdev[k][col];
+        cpart[part][col] = t;
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            double u = 0.0;
+            for (int q = 0; q < 16; ++q) u += cpart[q][threadIdx.x];
+            dsum[threadIdx.x] = u;
+        }
     }
     __syncthreads();
     double ss[4];  // sums of squared deviations from the means over the n blocks
@@ -2420,7 +2467,6 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init) {
 
 hipError_t launch_reduce(const LaunchCtx &c) {
     PA_LAUNCH(k_reduce, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
-    PA_LAUNCH(k_record, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
     return hipSuccess;
 }
 
@@ -2700,7 +2746,6 @@ hipError_t launch_weighted(const LaunchCtx &c, int first, int count, pa_weighted
 
 hipError_t launch_counts(const LaunchCtx &c) {
     PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
-    PA_LAUNCH(k_jack_weights, dim3(c.n_runs * kBlocks), dim3(256), 0, c.stream, c.runs);
     if (c.any_nearest)
         PA_LAUNCH(k_counts_nearest, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
@@ -2709,14 +2754,11 @@ hipError_t launch_counts(const LaunchCtx &c) {
     if (c.any_multi) {
         PA_LAUNCH(k_multi_weights, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
-        PA_LAUNCH(k_multi_cum, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
-                  c.slots.map);
-        PA_LAUNCH(k_multi_draw, dim3(c.slots.total * kDrawSplit), dim3(256), 0, c.stream, c.runs,
-                  c.slots.map);
-        PA_LAUNCH(k_count_partials, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
-                  c.slots.map);
+        PA_LAUNCH(k_multi_draw, dim3(c.slots.total), dim3(kSlotBlock), draw_lds_bytes(c.max_nblk),
+                  c.stream, c.runs, c.slots.map);
     }
-    PA_LAUNCH(k_offsets, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
+    PA_LAUNCH(k_offsets, dim3(c.slots.total + c.n_runs * kBlocks), dim3(256), 0, c.stream, c.runs,
+              c.slots.map, c.slots.total);
     return hipSuccess;
 }
 
@@ -2811,6 +2853,12 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream) {
 }
 
 hipError_t configure_kernels() {
+    // multinomial draws: 12 bytes of LDS per parent block, at most 8192 blocks (R < 2^23)
+    {
+        hipError_t e = hipFuncSetAttribute((const void *)k_multi_draw,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 8192 * 12);
+        if (e != hipSuccess) return e;
+    }
     // up to kMaxSweepLds bytes of lattices (with their halo) per sweep block
     for (int k = 0; k < 48; ++k) {
         const void *f = sweep_kernel((k / 6) & 1, (k / 2) % 3, k % 2 + 1, (k / 12) & 1, k >= 24);
