@@ -170,7 +170,8 @@ __global__ void __launch_bounds__(256) k_hist(const RunDesc *runs, WorkMap map) 
 // built by the previous step's reduction.  With dB = beta_i - beta_{i-1}
 // (exact, double-double) and w_l = exp(-4 dB l) the Boltzmann factor of level
 // kmin + l relative to the lowest occupied energy E_min:
-//   S = sum_l n_l w_l,   ln Q_i = -dB E_min + ln(S / R_{i-1})          (Eq. Q)
+//   S = sum_l n_l w_l,   ln Q_i = -dB E_min + ln(S / R_{i-1})          (Eq. Q,
+//                        the logarithm taken by k_offsets, see log_q)
 //   nearest:     Z_l = ceil(2^32 R w_l / S) = ceil(2^32 tau_hat)      (Eq. taus)
 //   multinomial: q_l = floor(2^40 w_l)
 //   Poisson:     lambda_l = R w_l / S = tau_hat and e^{-lambda_l} = m 2^-e,
@@ -190,7 +191,7 @@ constexpr double kPoissonMargin = 0x1p-8;     // in units of U
 __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     const RunDesc &rd = runs[blockIdx.x];
     RunState *st = rd.st;
-    __shared__ double sh_hi[256], sh_lo[256];
+    __shared__ double sh_hi[4], sh_lo[4];
     __shared__ int amb_any, ok;
     const int i = st->step + 1;
     if (threadIdx.x == 0) {
@@ -213,52 +214,62 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     }
     __syncthreads();
     if (!ok) return;
-    const int last = blockDim.x - 1;  // computes the thresholds and ln Q beside its levels
-    if (threadIdx.x == last) {
-        const double b1 = rd.betas[i];
+    const int Rp = st->R_cur, kmin = st->kmin, kmax = st->kmax;
+    const int nlev = kmax - kmin + 1;
+    const double b1 = rd.betas[i];
+    const dd db = two_sum(b1, -rd.betas[i - 1]);
+    const bool exact = (db.hi == 0.0) || (nlev == 1);
+    // One double-double exponential per thread, all in the same code path:
+    // thread 0 (whose level weight is 1) takes e^{-4 beta_i} for the
+    // thresholds, thread t > 0 its first level weight w_t = e^{-4 dbeta t}.
+    dd e{1.0, 0.0};
+    bool e_ok = true;
+    if (threadIdx.x == 0 ? b1 != 0.0 : !exact)
+        e_ok = dd_exp_neg(threadIdx.x == 0 ? dd{4.0 * b1, 0.0} : dd_mul_d(db, 4.0 * threadIdx.x), &e);
+    dd w = threadIdx.x == 0 ? dd{1.0, 0.0} : e;
+    if (threadIdx.x == 0) {
         if (b1 == 0.0) {
             st->t4 = st->t8 = 1ull << 32;  // heatbath: every flip has probability 1/2
         } else if (rd.update == PA_UPDATE_HEATBATH) {
             // T'_dE = floor(2^32 q / (1 + q)), q = e^{-beta dE}, dE = 4, 8: the
             // dE > 0 classes flip iff u <= T', the dE < 0 classes iff ~u >= T'
-            dd q4;
             bool amb = false;
-            if (!dd_exp_neg(dd{4.0 * b1, 0.0}, &q4)) {
+            if (!e_ok) {
                 st->t4 = st->t8 = 0;  // q < 2^-1000
             } else {
-                const dd q8 = dd_mul(q4, q4);
-                const dd p4 = dd_div(q4, dd_add(dd{1.0, 0.0}, q4));
+                const dd q8 = dd_mul(e, e);
+                const dd p4 = dd_div(e, dd_add(dd{1.0, 0.0}, e));
                 const dd p8 = dd_div(q8, dd_add(dd{1.0, 0.0}, q8));
                 st->t4 = dd_floor_decided(dd_ldexp(p4, 32), &amb);
                 st->t8 = p8.hi < 0x1p-990 ? 0 : dd_floor_decided(dd_ldexp(p8, 32), &amb);
             }
             if (amb) atomicOr(&amb_any, 1);
         } else {
-            dd p4;
             bool amb = false;
-            if (!dd_exp_neg(dd{4.0 * b1, 0.0}, &p4)) {
+            if (!e_ok) {
                 st->t4 = st->t8 = 1;  // 0 < p < 2^-1000
             } else {
-                const dd p8 = dd_mul(p4, p4);  // e^{-8 beta} = (e^{-4 beta})^2
-                st->t4 = dd_ceil_decided(dd_ldexp(p4, 32), &amb);
+                const dd p8 = dd_mul(e, e);  // e^{-8 beta} = (e^{-4 beta})^2
+                st->t4 = dd_ceil_decided(dd_ldexp(e, 32), &amb);
                 st->t8 = p8.hi < 0x1p-990 ? 1 : dd_ceil_decided(dd_ldexp(p8, 32), &amb);
             }
             if (amb) atomicOr(&amb_any, 1);
         }
     }
-    const int Rp = st->R_cur, kmin = st->kmin, kmax = st->kmax;
-    const int nlev = kmax - kmin + 1;
-    const dd db = two_sum(rd.betas[i], -rd.betas[i - 1]);
-    const bool exact = (db.hi == 0.0) || (nlev == 1);
-    // w_l = exp(-4 dbeta l): the thread's first level by exp, then repeated
-    // multiplication by exp(-4 dbeta blockDim) (at most nlev / blockDim double-
-    // double products, relative error far below the decision margin)
-    dd part{0.0, 0.0};
-    dd w{1.0, 0.0}, stride{1.0, 0.0};
-    if (!exact) {
-        if (threadIdx.x > 0) dd_exp_neg(dd_mul_d(db, 4.0 * threadIdx.x), &w);
-        if (nlev > (int)blockDim.x) dd_exp_neg(dd_mul_d(db, 4.0 * blockDim.x), &stride);
+    // Levels beyond the first blockDim: repeated multiplication by
+    // e^{-4 dbeta blockDim} = w_1 w_{blockDim-1} (at most nlev / blockDim
+    // double-double products; relative error far below the decision margin).
+    dd stride{1.0, 0.0};
+    if (!exact && nlev > (int)blockDim.x) {
+        if (threadIdx.x == 1 || threadIdx.x == blockDim.x - 1) {
+            sh_hi[threadIdx.x == 1 ? 0 : 1] = w.hi;
+            sh_lo[threadIdx.x == 1 ? 0 : 1] = w.lo;
+        }
+        __syncthreads();
+        stride = dd_mul(dd{sh_hi[0], sh_lo[0]}, dd{sh_hi[1], sh_lo[1]});
+        __syncthreads();
     }
+    dd part{0.0, 0.0};
     for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
         rd.wlev[2 * l] = w.hi;
         rd.wlev[2 * l + 1] = w.lo;
@@ -279,17 +290,7 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
     __syncthreads();
     const dd S = dd_add(dd_add(dd{sh_hi[0], sh_lo[0]}, dd{sh_hi[1], sh_lo[1]}),
                         dd_add(dd{sh_hi[2], sh_lo[2]}, dd{sh_hi[3], sh_lo[3]}));
-    if (threadIdx.x == last) {
-        const double e_min = -2.0 * rd.N + 4.0 * kmin;
-        dd lnq;
-        if (exact && db.hi == 0.0) {
-            lnq = dd{0.0, 0.0};
-        } else {
-            dd a = dd_mul_d(db, -e_min);
-            lnq = dd_add(a, dd_log(dd_div_d(S, (double)Rp)));
-        }
-        st->lnq_hi = lnq.hi;
-        st->lnq_lo = lnq.lo;
+    if (threadIdx.x == 0) {  // ln Q_i itself is taken by k_offsets (log_q)
         st->s_hi = S.hi;
         st->s_lo = S.lo;
         st->kmin_step = kmin;  // k_offsets resets st->kmin while its jackknife blocks run
@@ -346,6 +347,23 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
 
 // ------------------------------------------------------------------ free-energy jackknife
 
+// ln Q_i = -dB E_min + ln(S / R_{i-1}) (Eq. Q) from the S of k_norm, taken
+// off k_norm's critical path by one thread of a k_offsets block; dB = 0 gives
+// exactly 0, and so does a single occupied level (S = R_{i-1}).
+__device__ void log_q(const RunDesc &rd) {
+    RunState *st = rd.st;
+    const int i = st->step + 1;
+    const dd db = two_sum(rd.betas[i], -rd.betas[i - 1]);
+    dd lnq{0.0, 0.0};
+    if (db.hi != 0.0) {
+        const double e_min = -2.0 * rd.N + 4.0 * st->kmin_step;
+        lnq = dd_add(dd_mul_d(db, -e_min), dd_log(dd_div_d(dd{st->s_hi, st->s_lo}, (double)st->R_cur)));
+    }
+    st->lnq_hi = lnq.hi;
+    st->lnq_lo = lnq.lo;
+}
+
+
 // Sec. "Conclusions" (last guideline) with Eq. free-emergy-estimator: sample k
 // of the jackknife of -beta F leaves block k of every parent population out
 // of every Q.  Block k of the population entering step i is the slot range
@@ -359,6 +377,7 @@ __device__ void jack_weights(const RunDesc &rd, int k) {
     RunState *st = rd.st;
     const int nF = min(kBlocks, rd.R);
     if (st->err || k >= nF) return;
+    if (k == 0 && threadIdx.x == 0) log_q(rd);
     __shared__ double shd[16];
     const int Rp = st->R_cur, kmin = st->kmin_step;
     const int lo = (int)((int64_t)k * Rp / nF), hi = (int)((int64_t)(k + 1) * Rp / nF);
@@ -737,18 +756,25 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
 
 // ------------------------------------------------------------------ copy / compaction
 
-// Bit networks of the multispin gather (compress and expand of a 64-bit word
-// under a selector, Hacker's Delight Sec. 7-4 / 7-5): six stages that move
-// bits by 1, 2, 4, 8, 16 and 32 places.  The per-stage move masks depend only
-// on the selector, so one child group computes them once (uniform, scalar
-// registers) and applies them to every site word.
-struct Network {
-    uint64_t mv[6];
-    uint64_t m;  // the selector
+// Bit networks of the multispin gather.  Both run as six stages of the form
+// x = (x & ~g) | (y & g), y = x shifted by 2^i: one shift and one three-input
+// bitwise operation per 32-bit half, with the stage masks g computed once per
+// child group on the scalar unit (they depend only on the parents) and no
+// branches between the stages.
+//
+// Compress (the selected bits of x moved to the low end in order, Hacker's
+// Delight Sec. 7-4): the book's move masks mv_i, taken in gather form -- the
+// positions mv_i >> 2^i receive a moved bit at stage i.  Positions that a bit
+// leaves keep a stale copy, which no later stage reads (they only read
+// positions holding selected bits); the low popcount(m) bits are exact.
+struct Compress {
+    uint64_t g[6];
+    uint64_t low;  // the low popcount(m) bits
 };
-__device__ __forceinline__ Network network_masks(uint64_t m) {
-    Network n;
-    n.m = m;
+__device__ __forceinline__ Compress compress_masks(uint64_t m) {
+    Compress n;
+    const int cnt = __popcll(m);
+    n.low = cnt == 64 ? ~0ull : (1ull << cnt) - 1;
     uint64_t mk = ~m << 1;  // marks the zeros of m to the right of each bit
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -760,13 +786,11 @@ __device__ __forceinline__ Network network_masks(uint64_t m) {
         mp ^= mp << 32;
         const uint64_t mv = mp & m;
         m = (m ^ mv) | (mv >> (1 << i));
-        n.mv[i] = mv;
+        n.g[i] = mv >> (1 << i);
         mk &= ~mp;
     }
     return n;
 }
-// Selected bits of x, moved to the low end in order (bits of x outside the
-// selector are dropped).
 // A three-input bitwise function (table as for xor3) on the halves of 64-bit
 // words; the builtin returns a signed int, so each half is taken as unsigned
 // before it is widened
@@ -777,27 +801,32 @@ __device__ __forceinline__ uint64_t bitop3_64(uint64_t a, uint64_t b, uint64_t c
     const uint32_t lo = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, TABLE);
     return ((uint64_t)hi << 32) | lo;
 }
-// (a & ~b) | c and (a & ~b) | (c & b)
-__device__ __forceinline__ uint64_t andn_or(uint64_t a, uint64_t b, uint64_t c) { return bitop3_64<0xBA>(a, b, c); }
+// (a & ~b) | (c & b) and a | (b & c)
 __device__ __forceinline__ uint64_t select_bits(uint64_t a, uint64_t b, uint64_t c) { return bitop3_64<0xB8>(a, b, c); }
-__device__ __forceinline__ uint64_t net_compress(uint64_t x, const Network &n) {
-    x &= n.m;
+__device__ __forceinline__ uint64_t or_and(uint64_t a, uint64_t b, uint64_t c) { return bitop3_64<0xF8>(a, b, c); }
+// Compressed bits of x, not yet cut to the low popcount(m) bits.
+__device__ __forceinline__ uint64_t net_compress(uint64_t x, const Compress &n) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        if (n.mv[i]) {  // uniform
-            const uint64_t t = x & n.mv[i];
-            x = andn_or(x, n.mv[i], t >> (1 << i));  // (x ^ t) | (t >> 2^i)
-        }
-    }
+    for (int i = 0; i < 6; ++i) x = select_bits(x, n.g[i], x >> (1 << i));
     return x;
 }
-// The low bits of x, spread in order over the selector's positions.
-__device__ __forceinline__ uint64_t net_expand(uint64_t x, const Network &n) {
+// Spread with copies: child c (bit c of the child word) takes bit h(c) of the
+// distinct parents' bits S, where h(c) is the rank of c's parent among them.
+// The left shift d(c) = c - h(c) is the number of copies (children that repeat
+// the previous child's parent) at positions <= c: it never decreases and grows
+// by at most one per position.  Applying the shifts by 32, 16, ..., 1 in turn,
+// each where bit i of d is set at the stage's output position, then delivers
+// bit c - d(c) to every c: the value bound for c sits, before the stage of bit
+// i, at q = c - (d(c) mod 2^i), and d(q) lies in [d(c) - (c - q), d(c)], so
+// d(q) and d(c) agree in every bit from i up.
+struct Spread {
+    uint64_t s[6];  // s[i]: the children with bit i of d set
+    uint64_t live;  // the children that exist (the rest are written as 0)
+};
+__device__ __forceinline__ uint64_t net_spread(uint64_t x, const Spread &n) {
 #pragma unroll
-    for (int i = 5; i >= 0; --i) {
-        if (n.mv[i]) x = select_bits(x, n.mv[i], x << (1 << i));  // uniform test
-    }
-    return x & n.m;
+    for (int i = 5; i >= 0; --i) x = select_bits(x, n.s[i], x << (1 << i));
+    return x & n.live;
 }
 
 // Child c of destination group gd takes the spins and family label of parent
@@ -808,9 +837,8 @@ __device__ __forceinline__ uint64_t net_expand(uint64_t x, const Network &n) {
 //    few parent words.  Per parent group pg the surviving parents that feed
 //    this child group form a selector P_pg; compressing each parent word by
 //    P_pg and concatenating gives the distinct parents' bits S in order;
-//    expanding S onto the run heads D (children whose parent differs from
-//    the previous child's) and OR-filling each run of copies gives the child
-//    word.  Lane = four consecutive sites.
+//    spreading S over the children with their copies gives the child word.
+//    Lane = four consecutive sites.
 //  - int8: the parents' rows of kGatherSites sites at a time are staged in LDS
 //    (16-byte loads); thread = one dword (four children) of every 16th row.
 constexpr int kGatherPg = 4;      // int8: parent groups staged per pass
@@ -845,21 +873,6 @@ __device__ __forceinline__ bool gather_start(const RunDesc *runs, const WorkMap 
     return true;
 }
 
-// Child word of four sites from the concatenated surviving-parent bits S.
-__device__ __forceinline__ void gather_emit(const uint64_t *S, const Network &ND, uint64_t F,
-                                            uint64_t *o) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        uint64_t x = net_expand(S[k], ND);
-        uint64_t Fk = F;
-        for (int sh = 1; Fk; sh <<= 1) {  // OR-fill runs of copies (uniform)
-            x = bitop3_64<0xF8>(x, x << sh, Fk);  // x | ((x << sh) & Fk)
-            Fk &= Fk << sh;
-        }
-        o[k] = x;
-    }
-}
-
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -879,9 +892,15 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_msc64(const RunDesc *
     const gptr<u32x4> dst = global(reinterpret_cast<u32x4 *>(rd.ms[jb.nb] + (size_t)jb.gd * N));
     const int p_prev = __shfl_up(p, 1, 64);
     const bool live = lane < nv;
-    const uint64_t D = __ballot(live && (lane == 0 || p != p_prev));  // run heads
-    const uint64_t F = __ballot(live && lane > 0 && p == p_prev);     // copies after a head
-    const Network ND = network_masks(D);
+    // copies: children whose parent is the previous child's
+    const uint64_t F = __ballot(live && lane > 0 && p == p_prev);
+    Spread SP;
+    {
+        const int d = __popcll(F & ((2ull << lane) - 1));  // copies at lanes <= this one
+#pragma unroll
+        for (int i = 0; i < 6; ++i) SP.s[i] = __ballot(live && ((d >> i) & 1));
+        SP.live = __ballot(live);
+    }
     // the selector of parent group pg (its parents with a child in this group)
     // from the children's parents: an OR-scan of the bits 1 << (p mod 64) over
     // the lanes whose parent lies in the same group leaves it in the last such
@@ -906,17 +925,18 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_msc64(const RunDesc *
             const int l = __builtin_ctzll(m);
             const uint64_t P = readlane64(sel, l);
             const int pg = __builtin_amdgcn_readlane(pgl, l);
-            const Network NP = network_masks(P);
+            const Compress NP = compress_masks(P);
+            const uint64_t keep = NP.low << shift;  // where this group's parents land in S
             const gptr<const u32x4> sp = src + (size_t)pg * (N / 2);
 #pragma unroll
             for (int k = 0; k < kGatherPasses; ++k) {
                 const int sb = c0 + k * kGatherPass + 4 * lane;
                 if (sb < N) {
                     const u32x4 v0 = sp[sb / 2], v1 = sp[sb / 2 + 1];
-                    S[k][0] |= net_compress(((uint64_t)v0.y << 32) | v0.x, NP) << shift;
-                    S[k][1] |= net_compress(((uint64_t)v0.w << 32) | v0.z, NP) << shift;
-                    S[k][2] |= net_compress(((uint64_t)v1.y << 32) | v1.x, NP) << shift;
-                    S[k][3] |= net_compress(((uint64_t)v1.w << 32) | v1.z, NP) << shift;
+                    S[k][0] = or_and(S[k][0], net_compress(((uint64_t)v0.y << 32) | v0.x, NP) << shift, keep);
+                    S[k][1] = or_and(S[k][1], net_compress(((uint64_t)v0.w << 32) | v0.z, NP) << shift, keep);
+                    S[k][2] = or_and(S[k][2], net_compress(((uint64_t)v1.y << 32) | v1.x, NP) << shift, keep);
+                    S[k][3] = or_and(S[k][3], net_compress(((uint64_t)v1.w << 32) | v1.z, NP) << shift, keep);
                 }
             }
             shift += __popcll(P);
@@ -926,7 +946,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_msc64(const RunDesc *
             const int sb = c0 + k * kGatherPass + 4 * lane;
             if (sb < N) {
                 uint64_t o[4];
-                gather_emit(S[k], ND, F, o);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[q] = net_spread(S[k][q], SP);
                 dst[sb / 2] = u32x4{(uint32_t)o[0], (uint32_t)(o[0] >> 32), (uint32_t)o[1],
                                     (uint32_t)(o[1] >> 32)};
                 dst[sb / 2 + 1] = u32x4{(uint32_t)o[2], (uint32_t)(o[2] >> 32), (uint32_t)o[3],
