@@ -801,9 +801,8 @@ __device__ __forceinline__ uint64_t bitop3_64(uint64_t a, uint64_t b, uint64_t c
     const uint32_t lo = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, TABLE);
     return ((uint64_t)hi << 32) | lo;
 }
-// (a & ~b) | (c & b) and a | (b & c)
+// (a & ~b) | (c & b)
 __device__ __forceinline__ uint64_t select_bits(uint64_t a, uint64_t b, uint64_t c) { return bitop3_64<0xB8>(a, b, c); }
-__device__ __forceinline__ uint64_t or_and(uint64_t a, uint64_t b, uint64_t c) { return bitop3_64<0xF8>(a, b, c); }
 // Compressed bits of x, not yet cut to the low popcount(m) bits.
 __device__ __forceinline__ uint64_t net_compress(uint64_t x, const Compress &n) {
 #pragma unroll
@@ -821,12 +820,13 @@ __device__ __forceinline__ uint64_t net_compress(uint64_t x, const Compress &n) 
 // d(q) and d(c) agree in every bit from i up.
 struct Spread {
     uint64_t s[6];  // s[i]: the children with bit i of d set
-    uint64_t live;  // the children that exist (the rest are written as 0)
+    uint64_t live;  // the children that exist
 };
+// Dead children (past the population) come out unspecified.
 __device__ __forceinline__ uint64_t net_spread(uint64_t x, const Spread &n) {
 #pragma unroll
     for (int i = 5; i >= 0; --i) x = select_bits(x, n.s[i], x << (1 << i));
-    return x & n.live;
+    return x;
 }
 
 // Child c of destination group gd takes the spins and family label of parent
@@ -917,37 +917,48 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_msc64(const RunDesc *
     const uint64_t ends = __ballot(live && (lane == nv - 1 || pg_next != pgl));
     // chunks of kGatherPasses passes of a wavefront: per feeding parent group
     // (ascending), its network once and the compressed parent words of every
-    // pass, concatenated in S
+    // pass, concatenated in S.  Bits of S above the distinct parents may hold
+    // stale bits of the compress stages: the spread reads only bits h(c) of
+    // live children, and dead children are cleared at the end.
     for (int c0 = wave * kGatherPass * kGatherPasses; c0 < N; c0 += nw * kGatherPass * kGatherPasses) {
-        uint64_t S[kGatherPasses][4] = {};
+        uint64_t S[kGatherPasses][4];
+        // per feeding group, the compressed words of the chunk's passes; past
+        // the last site the loads repeat the last four words (never stored)
         int shift = 0;
         for (uint64_t m = ends; m; m &= m - 1) {  // uniform
             const int l = __builtin_ctzll(m);
-            const uint64_t P = readlane64(sel, l);
-            const int pg = __builtin_amdgcn_readlane(pgl, l);
-            const Compress NP = compress_masks(P);
+            const Compress NP = compress_masks(readlane64(sel, l));
             const uint64_t keep = NP.low << shift;  // where this group's parents land in S
-            const gptr<const u32x4> sp = src + (size_t)pg * (N / 2);
+            const gptr<const u32x4> sp = src + (size_t)__builtin_amdgcn_readlane(pgl, l) * (N / 2);
 #pragma unroll
             for (int k = 0; k < kGatherPasses; ++k) {
-                const int sb = c0 + k * kGatherPass + 4 * lane;
-                if (sb < N) {
-                    const u32x4 v0 = sp[sb / 2], v1 = sp[sb / 2 + 1];
-                    S[k][0] = or_and(S[k][0], net_compress(((uint64_t)v0.y << 32) | v0.x, NP) << shift, keep);
-                    S[k][1] = or_and(S[k][1], net_compress(((uint64_t)v0.w << 32) | v0.z, NP) << shift, keep);
-                    S[k][2] = or_and(S[k][2], net_compress(((uint64_t)v1.y << 32) | v1.x, NP) << shift, keep);
-                    S[k][3] = or_and(S[k][3], net_compress(((uint64_t)v1.w << 32) | v1.z, NP) << shift, keep);
+                const int sb = min(c0 + k * kGatherPass + 4 * lane, N - 4);
+                const u32x4 v0 = sp[sb / 2], v1 = sp[sb / 2 + 1];
+                const uint64_t x[4] = {net_compress(((uint64_t)v0.y << 32) | v0.x, NP),
+                                       net_compress(((uint64_t)v0.w << 32) | v0.z, NP),
+                                       net_compress(((uint64_t)v1.y << 32) | v1.x, NP),
+                                       net_compress(((uint64_t)v1.w << 32) | v1.z, NP)};
+                if (shift == 0) {  // uniform: the first group
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) S[k][q] = x[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) S[k][q] = select_bits(S[k][q], keep, x[q] << shift);
                 }
             }
-            shift += __popcll(P);
+            shift += __popcll(NP.low);
         }
 #pragma unroll
         for (int k = 0; k < kGatherPasses; ++k) {
+            uint64_t o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = net_spread(S[k][q], SP);
+            if (nv < 64) {  // uniform: the last, partial child group
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[q] &= SP.live;
+            }
             const int sb = c0 + k * kGatherPass + 4 * lane;
             if (sb < N) {
-                uint64_t o[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) o[q] = net_spread(S[k][q], SP);
                 dst[sb / 2] = u32x4{(uint32_t)o[0], (uint32_t)(o[0] >> 32), (uint32_t)o[1],
                                     (uint32_t)(o[1] >> 32)};
                 dst[sb / 2 + 1] = u32x4{(uint32_t)o[2], (uint32_t)(o[2] >> 32), (uint32_t)o[3],
