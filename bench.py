@@ -252,6 +252,52 @@ def cpu_baseline(betas, energies):
             "host": host_cpu()}
 
 
+def cpu_config1(pa):
+    """The small workload in full on both sides: L=8, R=1000, beta 0 -> 0.44 in
+    101 steps, theta=10, nearest-integer resampling.  The oracle's whole run
+    (its copy counts timed apart) beside the device run of the same seed: the
+    integer sums of every record must agree exactly, -beta F to rounding."""
+    import numpy as np
+    import torch
+    from oracle import pa_oracle as po
+    from workloads import linear_schedule
+    L1, R1, n1, seed1 = 8, 1000, 101, SEED
+    betas = linear_schedule(0.44, n1)
+    o = po.OracleRun(L1, R1, THETA, seed1, "nearest", np.asarray(betas, dtype=np.float64))
+    t_counts = [0.0]
+    counts = o.copy_counts
+
+    def timed_counts(*a, **k):
+        t = time.perf_counter()
+        r = counts(*a, **k)
+        t_counts[0] += time.perf_counter() - t
+        return r
+    o.copy_counts = timed_counts
+    t0 = time.perf_counter()
+    for _ in range(n1):
+        o.anneal_step()
+    t_oracle = time.perf_counter() - t0
+    attempts = sum(rec.R_i for rec in o.records[1:]) * L1 * L1 * THETA
+    run = pa.Run(L1, R1, betas, THETA, seed1, "nearest", "msc64")
+    run.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run.run(n1)
+    run.sync()
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t1
+    keys = ("R_i", "sum_E", "sum_E2", "sum_absM", "sum_M2", "n_families", "sum_cnt2")
+    same = all(run.observables(i)[k] == getattr(o.records[i], k) for i in range(n1 + 1) for k in keys)
+    f_gpu, f_orc = run.observables(n1)["minus_beta_F"], o.records[n1].minus_beta_F
+    run.close()
+    return {"workload": "L=8, R=1000, beta 0->0.44 in 101 steps, theta=10, nearest, seed %d" % seed1,
+            "oracle_seconds": t_oracle, "oracle_attempts_per_ns": attempts / t_oracle / 1e9,
+            "oracle_copy_counts_us_per_step": t_counts[0] / n1 * 1e6,
+            "gpu_seconds": t_gpu, "gpu_attempts_per_ns": attempts / t_gpu / 1e9,
+            "same_integer_sums_every_step": bool(same),
+            "minus_beta_F_rel_diff": abs(f_gpu - f_orc) / abs(f_orc)}
+
+
 def host_cpu() -> dict:
     """The host's CPU model and the cores this process may use; the oracle
     stays single-threaded, and value x cores is the host's ideal aggregate
@@ -477,6 +523,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(betas, energies_mid)
         out["cpu_baseline"]["host"]["ideal_aggregate_attempts_per_ns"] = (
             out["cpu_baseline"]["value"] * out["cpu_baseline"]["host"]["usable_cpus"])
+        log("timing the small workload in full on the oracle and the device")
+        out["cpu_baseline"]["small_workload_in_full"] = cpu_config1(pa)
     print(json.dumps(out))
 
 
