@@ -435,6 +435,18 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         pa_status e = upload_class_map(B, (int)k);
         if (e) return e;
     }
+    if (lc.sweep_classes.size() > 1) {  // the classes' sweeps side by side
+        for (size_t k = 0; k < lc.sweep_classes.size(); ++k) {
+            hipStream_t s = nullptr;
+            PA_HIP(B, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            lc.class_streams.push_back(s);
+        }
+        for (size_t k = 0; k <= lc.sweep_classes.size(); ++k) {
+            hipEvent_t ev = nullptr;
+            PA_HIP(B, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            lc.class_events.push_back(ev);
+        }
+    }
     lc.max_nblk = 1;  // multinomial runs (R < 2^23): at most 8192 blocks, 64 KiB of draw LDS
     for (int r = 0; r < n; ++r)
         if (cfgs[r].resample == PA_RESAMPLE_MULTINOMIAL)
@@ -551,6 +563,8 @@ pa_status engine_observables(pa_batch *B, int r, int step, pa_obs *out) {
 
 void engine_destroy(pa_batch *B) {
     for (hipEvent_t ev : B->events) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : B->lc.class_events) (void)hipEventDestroy(ev);
+    for (hipStream_t s : B->lc.class_streams) (void)hipStreamDestroy(s);
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
 }

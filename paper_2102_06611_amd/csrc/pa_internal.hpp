@@ -32,6 +32,11 @@ struct LaunchCtx {
     MapInfo slots;   // per run: nblk blocks of kSlotBlock slots
     MapInfo groups;  // per run: G blocks, one per 64-replica group
     std::vector<SweepClass> sweep_classes;  // one launch per distinct L
+    // with several classes: one stream per class (default priority), forked
+    // from and joined back to `stream` by events, so the classes' sweeps run
+    // side by side (also inside a captured graph)
+    std::vector<hipStream_t> class_streams;
+    std::vector<hipEvent_t> class_events;  // [0] fork, [1 + k] class k done
     bool any_nearest, any_multi, any_poisson;
     bool any_msc, any_int8;  // layouts present in the batch
     bool any_update[2];      // spin-update rules present in the batch (PA_UPDATE_*)

@@ -2477,7 +2477,19 @@ static const void *sweep_kernel(int layout, int walk, int ilp, int upd, bool cou
 }
 
 hipError_t launch_sweeps(const LaunchCtx &c, int init) {
-    for (const auto &cls : c.sweep_classes) {
+    const size_t nc = c.sweep_classes.size();
+    const bool fork = nc > 1 && c.class_streams.size() == nc && c.class_events.size() == nc + 1;
+    if (fork) {
+        hipError_t e = hipEventRecord(c.class_events[0], c.stream);
+        if (e != hipSuccess) return e;
+    }
+    for (size_t k = 0; k < nc; ++k) {
+        const auto &cls = c.sweep_classes[k];
+        hipStream_t stream = fork ? c.class_streams[k] : c.stream;
+        if (fork) {
+            hipError_t e = hipStreamWaitEvent(stream, c.class_events[0], 0);
+            if (e != hipSuccess) return e;
+        }
         const size_t lds = sweep_lds_bytes(cls.L, cls.gpb);
         const bool rows = cls.threads % (cls.L / 2) == 0;  // the word walk moves whole rows
         const int walk = !rows ? kWalkAny : cls.gpb == 1 ? kWalkOneGroup : kWalkRows;
@@ -2489,10 +2501,18 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init) {
                 if (!c.any_update[upd]) continue;
                 const void *fn = sweep_kernel(layout, walk, ilp, upd, c.count_calls);
                 void *args[] = {(void *)&c.runs, (void *)&cls.map, (void *)&init, (void *)&cls.gpb};
-                hipError_t e = hipLaunchKernel(fn, dim3(cls.total), dim3(cls.threads), args, lds, c.stream);
+                hipError_t e = hipLaunchKernel(fn, dim3(cls.total), dim3(cls.threads), args, lds, stream);
                 if (e != hipSuccess) return e;
             }
         }
+        if (fork) {
+            hipError_t e = hipEventRecord(c.class_events[1 + k], stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    for (size_t k = 0; fork && k < nc; ++k) {
+        hipError_t e = hipStreamWaitEvent(c.stream, c.class_events[1 + k], 0);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
