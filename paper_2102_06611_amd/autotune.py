@@ -1,9 +1,11 @@
 """Autotuner for the sweep kernel's launch geometry.
 
 The sweep kernel keeps whole 64-replica lattices in LDS; its free parameters
-are the threads per block and the number of 64-replica groups per block
-(small lattices leave threads idle unless several groups share a block);
-the variant field of the ABI is kept at 0.  The
+are the threads per block, the number of 64-replica groups per block (small
+lattices leave threads idle unless several groups share a block) and the
+words each thread updates at once (the ABI's variant: one, or two with their
+Philox chains interleaved, which trades occupancy for instruction-level
+parallelism).  The
 random numbers are keyed by replica and site, so every geometry must produce
 the same population: the tuner checks that bit for bit while it times each
 candidate from one snapshot, and stores the fastest per (arch, L, R bucket,
@@ -40,7 +42,7 @@ def key(L: int, R: int, layout: str) -> str:
 
 
 def candidates(L: int) -> List[Tuple[int, int, int]]:
-    """(threads, groups per block, variant) triples worth timing (variant is 0)."""
+    """(threads, groups per block, words per thread) triples worth timing."""
     N = L * L
     lds = (L + 2) * (L + 2) * 8  # one lattice with its halo
     out = []
@@ -50,7 +52,8 @@ def candidates(L: int) -> List[Tuple[int, int, int]]:
         if gpb > 1 and (gpb // 2) * N // 2 >= 1024:
             continue  # one group already fills a 1024-thread block
         for threads in (128, 256, 512, 1024):
-            out.append((threads, gpb, 0))
+            for words in (1, 2):
+                out.append((threads, gpb, words))
     return out
 
 

@@ -960,7 +960,7 @@ static pa_status set_sweep_launch(pa_batch *B, int32_t L, int32_t threads, int32
     if (B->dead) return fail(B, PA_ERR_DEVICE, "handle is unusable after a device error");
     if (threads < 64 || threads > 1024 || threads % 64) return fail(B, PA_ERR_ARG, "threads must be a multiple of 64 in [64, 1024]");
     if (gpb < 1 || gpb > 8) return fail(B, PA_ERR_ARG, "groups_per_block must be in [1, 8]");
-    if (variant != 0) return fail(B, PA_ERR_ARG, "variant must be 0");
+    if (variant < 0 || variant > 2) return fail(B, PA_ERR_ARG, "variant must be 0, 1 or 2");
     if (sweep_lds_bytes(L, gpb) > (size_t)kMaxSweepLds)
         return fail(B, PA_ERR_ARG, "groups_per_block * (L + 2)^2 * 8 bytes exceed the LDS budget");
     for (size_t k = 0; k < B->lc.sweep_classes.size(); ++k) {
@@ -969,6 +969,7 @@ static pa_status set_sweep_launch(pa_batch *B, int32_t L, int32_t threads, int32
         PA_HIP(B, hipStreamSynchronize(B->stream));
         sc.threads = threads;
         sc.gpb = gpb;
+        sc.words = variant;
         pa_status e = upload_class_map(B, (int)k);
         if (e) return e;
         PA_HIP(B, hipStreamSynchronize(B->stream));
@@ -990,7 +991,7 @@ static pa_status get_sweep_launch(pa_batch *B, int32_t L, int32_t *threads, int3
         if (sc.L != L) continue;
         if (threads) *threads = sc.threads;
         if (gpb) *gpb = sc.gpb;
-        if (variant) *variant = 0;
+        if (variant) *variant = sc.words;
         return PA_OK;
     }
     return fail(B, PA_ERR_ARG, "no run with this L");

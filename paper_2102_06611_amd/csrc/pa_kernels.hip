@@ -2494,7 +2494,8 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init) {
         const bool rows = cls.threads % (cls.L / 2) == 0;  // the word walk moves whole rows
         const int walk = !rows ? kWalkAny : cls.gpb == 1 ? kWalkOneGroup : kWalkRows;
         // a block that fills a CU's LDS runs alone: two words per thread at once
-        const int ilp = lds > kMaxSweepLds / 2 ? 2 : 1;
+        // (unless the launch geometry fixes the number)
+        const int ilp = cls.words ? cls.words : lds > kMaxSweepLds / 2 ? 2 : 1;
         for (int layout = 0; layout < 2; ++layout) {
             if (!(layout == PA_LAYOUT_MSC64 ? cls.has_msc : cls.has_int8)) continue;
             for (int upd = 0; upd < 2; ++upd) {

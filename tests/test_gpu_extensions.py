@@ -363,17 +363,19 @@ GEOMETRIES = {
 def test_sweep_geometry_does_not_change_results(L, update):
     betas = linear_schedule(0.5, 4)
     states = []
-    for threads, gpb in GEOMETRIES[L]:
-        r = pa.Run(L, 1000, betas, 3, 61, "nearest", "msc64", update=update)
-        r.set_sweep_launch(L, threads, gpb)
-        assert r.sweep_launch(L) == (threads, gpb, 0)
-        r.run(4)
-        states.append(r.get_state())
-        r.close()
+    for k, (threads, gpb) in enumerate(GEOMETRIES[L]):
+        for words in (0, 1 + k % 2):  # the default, and one or two words per thread
+            r = pa.Run(L, 1000, betas, 3, 61, "nearest", "msc64", update=update)
+            r.set_sweep_launch(L, threads, gpb, words)
+            assert r.sweep_launch(L) == (threads, gpb, words)
+            r.run(4)
+            states.append(r.get_state())
+            r.close()
     assert all(s == states[0] for s in states)
     r = pa.Run(L, 64, betas, 3, 61, "nearest", "msc64")
-    with pytest.raises(pa.PAError):
-        r.set_sweep_launch(L, 256, 1, 1)  # only variant 0 exists
+    for words in (-1, 3):
+        with pytest.raises(pa.PAError):
+            r.set_sweep_launch(L, 256, 1, words)
     r.close()
 
 
