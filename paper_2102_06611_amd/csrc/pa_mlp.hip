@@ -34,16 +34,22 @@ __device__ __forceinline__ void mlp_load(const float *P, int j, MlpLane &m) {
     m.b3 = P[oB3];
 }
 
+// Lane k's value of v in every lane (k uniform: one v_readlane into a scalar
+// register instead of a round trip through LDS).
+__device__ __forceinline__ float lane_value(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
 // One row through the network; xk = feature k held by lane k (k < 35).
 // Returns y in every lane; h1, h2 = this lane's hidden activations.
 __device__ __forceinline__ float mlp_row(const MlpLane &m, float xk, float *h1o, float *h2o) {
     float a = m.b1;
 #pragma unroll
-    for (int k = 0; k < kIn; ++k) a += m.w1[k] * __shfl(xk, k, 64);
+    for (int k = 0; k < kIn; ++k) a = fmaf(m.w1[k], lane_value(xk, k), a);
     const float h1 = tanhf(a);
     float b = m.b2;
 #pragma unroll
-    for (int k = 0; k < kH; ++k) b += m.w2[k] * __shfl(h1, k, 64);
+    for (int k = 0; k < kH; ++k) b = fmaf(m.w2[k], lane_value(h1, k), b);
     const float h2 = tanhf(b);
     float y = m.w3 * h2;
 #pragma unroll
@@ -68,15 +74,17 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *P, const float
     }
 }
 
-// Gradient of (1/n) sum (y - t)^2 by backpropagation, one block of four
-// wavefronts; per-wave partial gradients are summed in wave order in LDS
+// Gradient of (1/n) sum (y - t)^2 by backpropagation, one block of
+// kGradWaves wavefronts (two per SIMD, so one hides the other's dependent
+// FMA chains); per-wave partial gradients are summed in wave order in LDS
 // (deterministic).  mode 0 writes grad and loss; mode 1 applies one Adam step.
-__global__ void __launch_bounds__(256) k_mlp_grad(float *P, const float *X, const float *T, int n,
+constexpr int kGradWaves = 8;
+__global__ void __launch_bounds__(kGradWaves * 64) k_mlp_grad(float *P, const float *X, const float *T, int n,
                                                   float *grad, float *loss, float *adam, float lr,
                                                   int t, int mode) {
     __shared__ float W2s[kH * kH];
     __shared__ float G[PA_MLP_PARAMS];
-    __shared__ float Ls[4];
+    __shared__ float Ls[kGradWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < kH * kH; k += blockDim.x) W2s[k] = P[oW2 + k];
     for (int k = threadIdx.x; k < PA_MLP_PARAMS; k += blockDim.x) G[k] = 0.0f;
@@ -90,7 +98,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(float *P, const float *X, cons
     for (int k = 0; k < kH; ++k) gw2[k] = 0.0f;
     float gb1 = 0, gb2 = 0, gw3 = 0, gb3 = 0, lsum = 0;
     const float inv_n = 1.0f / (float)n;
-    for (int row = wave; row < n; row += 4) {
+    for (int row = wave; row < n; row += kGradWaves) {
         const float xk = lane < kIn ? X[(size_t)row * kIn + lane] : 0.0f;
         float h1, h2;
         const float y = mlp_row(m, xk, &h1, &h2);
@@ -102,16 +110,16 @@ __global__ void __launch_bounds__(256) k_mlp_grad(float *P, const float *X, cons
         const float d2 = g * m.w3 * (1.0f - h2 * h2);
         gb2 += d2;
 #pragma unroll
-        for (int k = 0; k < kH; ++k) gw2[k] += d2 * __shfl(h1, k, 64);
+        for (int k = 0; k < kH; ++k) gw2[k] = fmaf(d2, lane_value(h1, k), gw2[k]);
         float s = 0.0f;  // sum_j d2_j W2[j][lane]
 #pragma unroll
-        for (int j = 0; j < kH; ++j) s += __shfl(d2, j, 64) * W2s[j * kH + lane];
+        for (int j = 0; j < kH; ++j) s = fmaf(lane_value(d2, j), W2s[j * kH + lane], s);
         const float d1 = s * (1.0f - h1 * h1);
         gb1 += d1;
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) gw1[k] += d1 * __shfl(xk, k, 64);
+        for (int k = 0; k < kIn; ++k) gw1[k] = fmaf(d1, lane_value(xk, k), gw1[k]);
     }
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < kGradWaves; ++w) {
         if (wave == w) {
 #pragma unroll
             for (int k = 0; k < kIn; ++k) G[oW1 + lane * kIn + k] += gw1[k];
@@ -141,7 +149,11 @@ __global__ void __launch_bounds__(256) k_mlp_grad(float *P, const float *X, cons
             P[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
         }
     }
-    if (threadIdx.x == 0 && loss) loss[0] = Ls[0] + Ls[1] + Ls[2] + Ls[3];
+    if (threadIdx.x == 0 && loss) {
+        float l = 0.0f;
+        for (int w = 0; w < kGradWaves; ++w) l += Ls[w];
+        loss[0] = l;
+    }
 }
 
 // Features of the current population from its energy histogram: 32 bins of
@@ -309,14 +321,14 @@ hipError_t launch_mlp_forward(const float *params, const float *x, int n, float 
 
 hipError_t launch_mlp_backward(const float *params, const float *x, const float *t, int n,
                                float *grad, float *loss, hipStream_t stream) {
-    hipLaunchKernelGGL(k_mlp_grad, dim3(1), dim3(256), 0, stream, const_cast<float *>(params), x,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(1), dim3(kGradWaves * 64), 0, stream, const_cast<float *>(params), x,
                        t, n, grad, loss, (float *)nullptr, 0.0f, 0, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_adam_step(float *params, float *adam, const float *x, const float *t, int n,
                             float lr, int step, float *loss, hipStream_t stream) {
-    hipLaunchKernelGGL(k_mlp_grad, dim3(1), dim3(256), 0, stream, params, x, t, n,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(1), dim3(kGradWaves * 64), 0, stream, params, x, t, n,
                        (float *)nullptr, loss, adam, lr, step, 1);
     return hipGetLastError();
 }
