@@ -243,8 +243,7 @@ pa_status pa_profile_read(pa_ctx *ctx, int32_t *n_steps, double *ms_resample, do
  * (1..8, with groups_per_block * (L + 2)^2 * 8 bytes <= 152 KiB of LDS: each
  * lattice is held with a one-site halo).  variant: the 64-replica words each
  * thread updates at once, their Philox chains interleaved: 1 or 2, or 0 for
- * the default (2 when a block's lattices need more than half of that LDS, else
- * 1); other values give PA_ERR_ARG.  The results do not depend on the geometry
+ * the default (1); other values give PA_ERR_ARG.  The results do not depend on the geometry
  * (the random numbers are keyed by replica and site); only speed does.
  * Synchronises. */
 pa_status pa_set_sweep_launch(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_block,

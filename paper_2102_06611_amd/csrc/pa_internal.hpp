@@ -23,7 +23,7 @@ struct SweepClass {
     bool has_msc, has_int8;
     int threads;  // block size of k_sweep for this lattice size
     int gpb;      // 64-replica groups per block
-    int words = 0;  // words each thread updates at once: 0 = by LDS size, 1 or 2
+    int words = 0;  // words each thread updates at once: 0 = default (1), 1 or 2
 };
 
 struct LaunchCtx {

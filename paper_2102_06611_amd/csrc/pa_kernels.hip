@@ -2493,9 +2493,10 @@ hipError_t launch_sweeps(const LaunchCtx &c, int init) {
         const size_t lds = sweep_lds_bytes(cls.L, cls.gpb);
         const bool rows = cls.threads % (cls.L / 2) == 0;  // the word walk moves whole rows
         const int walk = !rows ? kWalkAny : cls.gpb == 1 ? kWalkOneGroup : kWalkRows;
-        // a block that fills a CU's LDS runs alone: two words per thread at once
-        // (unless the launch geometry fixes the number)
-        const int ilp = cls.words ? cls.words : lds > kMaxSweepLds / 2 ? 2 : 1;
+        // words each thread updates at once: one unless the launch geometry asks
+        // for two (their Philox chains interleaved; measured no faster at L = 64
+        // or 128, where one block fills a CU's LDS)
+        const int ilp = cls.words ? cls.words : 1;
         for (int layout = 0; layout < 2; ++layout) {
             if (!(layout == PA_LAYOUT_MSC64 ? cls.has_msc : cls.has_int8)) continue;
             for (int upd = 0; upd < 2; ++upd) {
