@@ -135,6 +135,11 @@ CASES = [
     # boundaries (the first grows one family over five blocks)
     (6, 5000, 0, 6, 2.0, "nearest", "msc64"),
     (4, 5000, 1, 6, 3.0, "multinomial", "int8"),
+    (6, 5000, 0, 6, 2.0, "multinomial", "msc64"),
+    # one jump to beta = 5: a few parents fill whole 64-replica child groups
+    # (the multispin copy's spread network at its deepest shifts)
+    (4, 3000, 0, 2, 5.0, "nearest", "msc64"),
+    (4, 3000, 0, 2, 5.0, "multinomial", "msc64"),
     # Poisson resampling: fluctuating R_i, several blocks, strong selection
     (8, 200, 3, 8, 0.44, "poisson", "msc64"),
     (6, 130, 2, 6, 0.6, "poisson", "int8"),
