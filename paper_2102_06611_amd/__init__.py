@@ -10,8 +10,10 @@ The functions keep the C names (pa_create, pa_anneal_step, ...); ``Run`` and
 from __future__ import annotations
 
 import ctypes
+import json
+import math
 import os
-from typing import List, Optional, Sequence
+from typing import IO, Iterable, List, Optional, Sequence, Union
 
 import numpy as np
 
@@ -188,6 +190,8 @@ class Run:
         self.cfg, self._betas = make_config(L, R, betas, theta, seed, resample, layout,
                                             capacity, n_steps, update)
         self.max_steps = self.cfg.n_steps
+        self.meta = {"L": L, "R": R, "theta": theta, "seed": seed, "resample": resample,
+                     "layout": layout, "update": update}
         nbytes = ctypes.c_size_t()
         _check(lib().pa_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
         self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
@@ -226,6 +230,15 @@ class Run:
         o = pa_obs()
         _check(lib().pa_observables(self.h, int(step), ctypes.byref(o)), self.h)
         return o.as_dict()
+
+    def export_jsonl(self, dest: Union[str, IO[str]], first: int = 0,
+                     last: Optional[int] = None) -> int:
+        """Records first .. last (default: the current step) as JSON Lines, one
+        object per step with the run's configuration (write_jsonl)."""
+        if last is None:
+            last = self.current()[0]
+        return write_jsonl((self.observables(i) for i in range(first, last + 1)), dest,
+                           **self.meta)
 
     def current(self):
         s, r = ctypes.c_int32(), ctypes.c_int32()
@@ -373,6 +386,10 @@ class Batch:
             self._keep.append(arr)
         self.n = len(specs)
         self._L = [s["L"] for s in specs]
+        self.meta = [{"run": k, "L": s["L"], "R": s["R"], "theta": s["theta"], "seed": s["seed"],
+                      "resample": s.get("resample", "nearest"), "layout": s.get("layout", "msc64"),
+                      "update": s.get("update", "metropolis")} for k, s in enumerate(specs)]
+        self.steps = 0  # steps queued so far (every run advances together)
         nbytes = ctypes.c_size_t()
         _check(lib().pa_batch_workspace_size(cfgs, self.n, ctypes.byref(nbytes)))
         self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
@@ -384,6 +401,7 @@ class Batch:
 
     def run(self, n_steps: int):
         _check(lib().pa_batch_run(self.h, int(n_steps)), self.h, batch=True)
+        self.steps += int(n_steps)
 
     def set_sweep_launch(self, L: int, threads: int, groups_per_block: int, variant: int = 0):
         _check(lib().pa_batch_set_sweep_launch(self.h, L, threads, groups_per_block, variant),
@@ -417,6 +435,18 @@ class Batch:
             E.ctypes.data_as(_P(_i32)), M.ctypes.data_as(_P(_i32))), self.h, batch=True)
         return s, fam, E, M
 
+    def export_jsonl(self, dest: Union[str, IO[str]], runs: Optional[Sequence[int]] = None,
+                     first: int = 0, last: Optional[int] = None) -> int:
+        """Records first .. last (default: the last queued step) of the given runs
+        (default: all) as JSON Lines, run by run, each object carrying its run's
+        index and configuration (write_jsonl)."""
+        if last is None:
+            last = self.steps
+        runs = range(self.n) if runs is None else runs
+        recs = ({**self.meta[r], **self.observables(r, i)} for r in runs
+                for i in range(first, last + 1))
+        return write_jsonl(recs, dest)
+
     def weighted(self, first: int, count: int = 1) -> List[dict]:
         """The runs combined at steps first .. first + count - 1 (pa_batch_weighted)."""
         import torch
@@ -439,6 +469,56 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+_NONFINITE = {"NaN": math.nan, "Infinity": math.inf, "-Infinity": -math.inf}
+
+
+def _json_value(v):
+    if isinstance(v, float) and not math.isfinite(v):
+        return "NaN" if math.isnan(v) else ("Infinity" if v > 0 else "-Infinity")
+    return v
+
+
+def write_jsonl(records: Iterable[dict], dest: Union[str, IO[str]], **extra) -> int:
+    """Per-step records (dicts from observables() or weighted()) as JSON Lines.
+
+    One strict-JSON object per line: the `extra` keys first (e.g. the run's
+    configuration), then the record's fields in their C order.  JSON has no
+    non-finite numbers, so NaN (a blocked error with fewer than two blocks) and
+    +-inf (R_eff of a population whose blocked variance is zero) are written as
+    the strings "NaN", "Infinity" and "-Infinity"; read_jsonl turns them back.
+    dest is a path (overwritten) or an open text file.  Returns the line count.
+    """
+    def emit(fh):
+        n = 0
+        for rec in records:
+            obj = {k: _json_value(v) for k, v in {**extra, **rec}.items()}
+            fh.write(json.dumps(obj, allow_nan=False) + "\n")
+            n += 1
+        return n
+
+    if isinstance(dest, (str, os.PathLike)):
+        with open(dest, "w") as fh:
+            return emit(fh)
+    return emit(dest)
+
+
+def read_jsonl(src: Union[str, IO[str]]) -> List[dict]:
+    """The records of a write_jsonl file, with non-finite values restored."""
+    def load(fh):
+        out = []
+        for line in fh:
+            if line.strip():
+                obj = json.loads(line)
+                out.append({k: _NONFINITE.get(v, v) if isinstance(v, str) else v
+                            for k, v in obj.items()})
+        return out
+
+    if isinstance(src, (str, os.PathLike)):
+        with open(src) as fh:
+            return load(fh)
+    return load(src)
 
 
 def philox4x32_10(key: int, ctr_dev, out_dev, stream=None):
