@@ -69,7 +69,7 @@ bool validate(const pa_config &c, std::string *why) {
 struct RunPlan {
     int L, N, R, C, G, K, nblk, max_steps;
     size_t off_ms[2], off_s8[2], off_E, off_M, off_fam[2], off_hist, off_zlev, off_wlev,
-        off_plev, off_cnt, off_off, off_par, off_cum, off_part, off_partd, off_blk, off_betas, off_records, off_st,
+        off_plev, off_cnt, off_off, off_par, off_cum, off_send, off_e8, off_part, off_partd, off_blk, off_betas, off_records, off_st,
         off_stage, off_feat, off_flog, off_tlog, off_alog, off_alpha, off_jkw;
     size_t bytes;
 };
@@ -112,6 +112,8 @@ RunPlan plan_run(const pa_config &c) {
     p.off_off = take((size_t)(p.C + 1) * 4);
     p.off_par = take((size_t)p.C * 4);
     p.off_cum = take((size_t)p.C * 8);
+    p.off_send = take((size_t)p.G * 8);
+    p.off_e8 = take((size_t)p.C);  // C / 8 entries of 8 bytes
     p.off_part = take((size_t)p.nblk * 8 * 8);
     p.off_partd = take((size_t)p.nblk * 2 * 8);
     p.off_blk = take((size_t)kBlocks * 4 * 8);
@@ -370,6 +372,8 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
         d.off = (int32_t *)(base + p.off_off);
         d.par = (int32_t *)(base + p.off_par);
         d.cum = (uint64_t *)(base + p.off_cum);
+        d.send = (uint64_t *)(base + p.off_send);
+        d.e8 = (uint64_t *)(base + p.off_e8);
         d.part = (int64_t *)(base + p.off_part);
         d.partd = (double *)(base + p.off_partd);
         d.blk = (int64_t *)(base + p.off_blk);

@@ -84,6 +84,8 @@ struct RunDesc {
     int32_t *off;              // [C + 1] exclusive offsets of the children
     int32_t *par;              // [C] parent of each child slot of the last resampling
     uint64_t *cum;             // [C] multinomial cumulative quantised weights
+    uint64_t *send;            // [C / 64] cum at the last parent of each stretch of 64
+    uint64_t *e8;              // [C / 8] cum at the last parent of each eighth of a stretch
     int64_t *part;             // [nblk * 4] per-block partial sums
     int64_t *blk;              // [kBlocks * 4] blocking sums of E, E^2, |M|, M^2 (zero between steps)
     double *partd;             // [nblk * 2] per-block FP partials

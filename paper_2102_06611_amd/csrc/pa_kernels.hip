@@ -541,22 +541,30 @@ __global__ void __launch_bounds__(256) k_counts_poisson(const RunDesc *runs, Wor
 }
 
 // Multinomial, pass 1: quantised weight q_j of each parent, its inclusive
-// prefix within the block of kSlotBlock parents (cum[j]), the block's total
-// (part[b*8 + 3]), zeroed counts and a zeroed per-block count (part[b*8 + 0],
-// which the draws increment).
+// prefix within the block of kSlotBlock parents (cum[j]), that prefix at the
+// last parent of each stretch of 64 and of each eighth of a stretch once more
+// in dense arrays (send[s], read whole by every block of the draws, and
+// e8[j / 8], whose eight entries for a stretch share one 64-byte segment), the
+// block's total (part[b*8 + 3]), zeroed counts and a zeroed per-block count
+// (part[b*8 + 0], which the draws increment).
 __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, WorkMap map) {
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
-    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
     __shared__ int64_t sh[32];
-    const int Rp = st->R_cur, kmin = st->kmin;
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
+    // the parents' energies (up to the capacity) load alongside the run's state
+    int32_t e[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (j + m < rd.C) e[m] = rd.E[j + m];
+    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    const int Rp = st->R_cur, kmin = st->kmin;
     uint64_t q[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         if (j + m < Rp) {
-            q[m] = rd.zlev[((rd.E[j + m] + 2 * rd.N) >> 2) - kmin];
+            q[m] = rd.zlev[((e[m] + 2 * rd.N) >> 2) - kmin];
             rd.cnt[j + m] = 0;
         }
     }
@@ -565,7 +573,11 @@ __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, Work
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         run += q[m];
-        if (j + m < Rp) rd.cum[j + m] = run;
+        if (j + m < Rp) {
+            rd.cum[j + m] = run;
+            if (((j + m) & 7) == 7 || j + m == Rp - 1) rd.e8[(j + m) >> 3] = run;
+            if (((j + m) & 63) == 63 || j + m == Rp - 1) rd.send[(j + m) >> 6] = run;
+        }
     }
     if (threadIdx.x == 0) {
         rd.part[b * 8 + 3] = tot;
@@ -591,6 +603,8 @@ __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, Work
 // ends of the block's sixteen stretches), then the eighth and the parent by
 // independent loads of the in-block prefix; its count and the block's LDS
 // count are incremented.
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));  // 16-byte loads
+
 __device__ __forceinline__ void draw_one(const RunDesc &rd, int d, int i, uint64_t W,
                                          const uint64_t *base, const uint64_t *coarse, int nc,
                                          int nbp, int Rp, int32_t *bcnt) {
@@ -615,21 +629,39 @@ __device__ __forceinline__ void draw_one(const RunDesc &rd, int d, int i, uint64
         }
         pb = lo;
         const uint64_t t = target - base[pb];
-        const int j0 = pb * kSlotBlock, lastb = min(j0 + kSlotBlock, Rp) - 1;
+        const int s_first = pb * (kSlotBlock / 64), s_last = (min(pb * kSlotBlock + kSlotBlock, Rp) - 1) >> 6;
+        const gptr<const uint64_t> send = global(static_cast<const uint64_t *>(rd.send));
         int e = 0;  // stretches of 64 whose last prefix is <= t
 #pragma unroll
-        for (int k = 0; k < 15; ++k) e += cum[min(j0 + 64 * k + 63, lastb)] <= t ? 1 : 0;
-        s0 = j0 + 64 * e;
+        for (int k = 0; k < kSlotBlock / 64 - 1; ++k) e += send[min(s_first + k, s_last)] <= t ? 1 : 0;
+        s0 = pb * kSlotBlock + 64 * e;
     }
     const uint64_t t = target - base[pb];  // below the block's total
     const int last = min(pb * kSlotBlock + kSlotBlock, Rp) - 1;
-    int e2 = 0;  // eighths of the stretch
+    // Each level reads one aligned 64-byte segment in four 16-byte loads: the
+    // eight eighth-ends of the stretch (e8), then the eight prefixes of the
+    // eighth (cum).  Entries past the block's last parent (a short final
+    // stretch) are stale and are not compared: the target lies below them.
+    const gptr<const u64x2> e8v = global(reinterpret_cast<const u64x2 *>(rd.e8 + (s0 >> 3)));
+    u64x2 q[4];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) e2 += cum[min(s0 + 8 * k + 7, last)] <= t ? 1 : 0;
+    for (int k = 0; k < 4; ++k) q[k] = e8v[k];
+    int e2 = 0;  // eighths of the stretch whose end is <= t
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const uint64_t v = (k & 1) ? q[k >> 1].y : q[k >> 1].x;
+        e2 += s0 + 8 * k <= last && v <= t ? 1 : 0;
+    }
     const int b0 = s0 + 8 * e2;
+    const gptr<const u64x2> cv = global(reinterpret_cast<const u64x2 *>(rd.cum + b0));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = cv[k];
     int f = 0;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) f += cum[min(b0 + k, last)] <= t ? 1 : 0;
+    for (int k = 0; k < 7; ++k) {
+        const uint64_t v = (k & 1) ? q[k >> 1].y : q[k >> 1].x;
+        f += b0 + k <= last && v <= t ? 1 : 0;
+    }
     atomicAdd(&rd.cnt[b0 + f], 1);
     atomicAdd(&bcnt[pb], 1);
 }
@@ -649,32 +681,49 @@ __global__ void __launch_bounds__(kSlotBlock) k_multi_draw(const RunDesc *runs, 
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
-    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
     extern __shared__ uint64_t base[];  // [nbp] bases, [nc] coarse index if used, [nbp] int32 counts
     __shared__ int64_t sh[32];
+    // Loads bounded by the capacity, issued before the run's state is known
+    // so that their latencies overlap: the parent-block total of this thread
+    // (one per thread while the capacity has at most blockDim blocks) and the
+    // stretch ends of the coarse index (at most kCoarse / blockDim each).
+    const int tid = (int)threadIdx.x;
+    const gptr<const uint64_t> send = global(static_cast<const uint64_t *>(rd.send));
+    const uint64_t part0 = tid < rd.nblk ? (uint64_t)rd.part[tid * 8 + 3] : 0;
+    constexpr int kSendPer = kCoarse / kSlotBlock;
+    uint64_t se[kSendPer];
+#pragma unroll
+    for (int m = 0; m < kSendPer; ++m) {
+        const int k = tid + m * kSlotBlock;
+        se[m] = k < min(rd.G, kCoarse) ? send[k] : 0;
+    }
+    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
     const int Rp = st->R_cur, i = st->step + 1;
     const int nbp = (Rp + kSlotBlock - 1) / kSlotBlock;
     const int nc = (Rp + 63) >> 6;
     uint64_t *coarse = nc <= kCoarse ? base + nbp : nullptr;
     int32_t *bcnt = reinterpret_cast<int32_t *>(base + nbp + (coarse ? nc : 0));
-    const int per = (nbp + (int)blockDim.x - 1) / (int)blockDim.x;  // blocks per thread
-    const int kb = (int)threadIdx.x * per, ke = min(kb + per, nbp);
+    const int per = (nbp + kSlotBlock - 1) / kSlotBlock;  // blocks per thread
+    const int kb = tid * per, ke = min(kb + per, nbp);
     uint64_t s = 0;
-    for (int k = kb; k < ke; ++k) s += (uint64_t)rd.part[k * 8 + 3];
+    if (per == 1) {
+        s = kb < nbp ? part0 : 0;
+    } else {
+        for (int k = kb; k < ke; ++k) s += (uint64_t)rd.part[k * 8 + 3];
+    }
     int64_t total;
     uint64_t acc = (uint64_t)block_exclusive_scan((int64_t)s, sh, &total);
     for (int k = kb; k < ke; ++k) {
         base[k] = acc;
         bcnt[k] = 0;
-        acc += (uint64_t)rd.part[k * 8 + 3];
+        acc += per == 1 ? part0 : (uint64_t)rd.part[k * 8 + 3];
     }
     __syncthreads();
     if (coarse) {
-        const gptr<const uint64_t> cum = global(static_cast<const uint64_t *>(rd.cum));
-#pragma unroll 8
-        for (int k = threadIdx.x; k < nc; k += blockDim.x) {
-            const int j = min(64 * k + 63, Rp - 1);
-            coarse[k] = base[j / kSlotBlock] + cum[j];
+#pragma unroll
+        for (int m = 0; m < kSendPer; ++m) {
+            const int k = tid + m * kSlotBlock;
+            if (k < nc) coarse[k] = base[k / (kSlotBlock / 64)] + se[m];
         }
         __syncthreads();
     }
@@ -701,24 +750,27 @@ __global__ void __launch_bounds__(256) k_offsets(const RunDesc *runs, WorkMap ma
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
-    if (st->err) return;
     __shared__ int64_t sh[32];
     __shared__ int64_t base_sh;
-    const int Rp = st->R_cur;
-    // this thread's four counts (loaded first: they do not depend on the sums)
+    // this thread's four counts and the parent blocks' child counts, loaded
+    // (up to the capacity) before the run's state, whose latency they share
     const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
     int c[4] = {0, 0, 0, 0};
     for (int m = 0; m < 4; ++m)
-        if (j + m < Rp) c[m] = rd.cnt[j + m];
-    // children of the blocks before this one and of all blocks (one pass); the
-    // block's sum of r_j^2 goes to the step's total
-    int64_t v[3] = {0, 0, (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2] +
-                              (int64_t)c[3] * c[3]};
+        if (j + m < rd.C) c[m] = rd.cnt[j + m];
+    // children of the blocks before this one and of all blocks (one pass)
+    int64_t v[3] = {0, 0, 0};
     for (int k = threadIdx.x; k < rd.nblk; k += blockDim.x) {
         const int64_t r = rd.part[k * 8 + 0];
         v[0] += k < b ? r : 0;
         v[1] += r;
     }
+    if (st->err) return;
+    const int Rp = st->R_cur;
+    for (int m = 0; m < 4; ++m)
+        if (j + m >= Rp) c[m] = 0;
+    // the block's sum of r_j^2 goes to the step's total
+    v[2] = (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2] + (int64_t)c[3] * c[3];
     block_sum_i64v(v, sh);
     if (threadIdx.x == 0) {
         base_sh = v[0];
@@ -1976,6 +2028,19 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
     int b;
     const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
     RunState *st = rd.st;
+    // the energies and magnetisations of this thread's four slots (up to the
+    // capacity) load alongside the run's state; the slots past R_i are unused
+    int32_t e_pre[4] = {0, 0, 0, 0}, m_pre[4] = {0, 0, 0, 0};
+    {
+        const int c = b * kSlotBlock + 4 * (int)threadIdx.x;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (c + m < rd.C) {
+                e_pre[m] = rd.E[c + m];
+                m_pre[m] = rd.M[c + m];
+            }
+        }
+    }
     if (st->err) return;
     __shared__ int64_t shv[4][6];
     __shared__ double shd[4];
@@ -2034,7 +2099,7 @@ __global__ void __launch_bounds__(256) k_reduce(const RunDesc *runs, WorkMap map
         const int c = c0 + m;
         if (c >= j1) break;
         if (is_start[m]) run_start = c;
-        const int64_t e = rd.E[c], mm = rd.M[c];
+        const int64_t e = e_pre[m], mm = m_pre[m];
         lev[m] = (int)((e + 2 * rd.N) >> 2);
         ev[m] = e;
         av[m] = mm < 0 ? -mm : mm;
