@@ -2194,6 +2194,21 @@ __device__ void record_run(const RunDesc &rd) {
     __shared__ double shd[32];
     const int Rn = st->R_new, nb = st->cur ^ 1;
     const int nblk = (Rn + kSlotBlock - 1) / kSlotBlock;
+    // Everything the record reads from the run's state and schedule, loaded
+    // before the first barrier so that the latencies overlap those of the
+    // blocks' partials (none of it changes during the reduction).
+    const int step = st->step + 1;
+    const double beta = rd.betas[step];
+    const int Rp = st->R_cur;  // the parents of this step
+    const double S = st->s_hi + st->s_lo;
+    const dd acc_prev{st->acc_hi, st->acc_lo}, lnq{st->lnq_hi, st->lnq_lo};
+    const int64_t sum_cnt2 = st->sum_cnt2;
+    const int nF = min(kBlocks, rd.R);
+    double jkF_own = 0.0, jkw_own = 0.0;
+    if ((int)threadIdx.x < nF) {
+        jkF_own = st->jk_F[threadIdx.x];
+        jkw_own = rd.jkw[threadIdx.x];
+    }
     // thread k < n: the blocking sums of block k (used below), cleared for the next step
     const int nbk = min(kBlocks, Rn);
     const bool own = (int)threadIdx.x < nbk;
@@ -2236,8 +2251,6 @@ __device__ void record_run(const RunDesc &rd) {
     }
     block_sum_i64v(T, sh);
     const double TCL = block_sum_f64(c, shd);
-    const int step = st->step + 1;
-    const double beta = rd.betas[step];
     const double Nd = (double)rd.N;
 
     // blocking and jackknife (Sec. "Effective population size", Eqs. blocks,
@@ -2254,16 +2267,13 @@ __device__ void record_run(const RunDesc &rd) {
     // beta F is beta F - D_k
     __shared__ int64_t tot_sh[4];
     __shared__ double bdev[kBlocks][16], dsum[16], dF[kBlocks];
-    const int nF = min(kBlocks, rd.R);
     if ((int)threadIdx.x < nF) {
         const int k = threadIdx.x;
-        double D = st->jk_F[k];
+        double D = jkF_own;
         if (step > 0) {
-            const int Rp = st->R_cur;  // the parents of this step
             const int64_t lo = (int64_t)k * Rp / nF, hi = (int64_t)(k + 1) * Rp / nF;
-            const double S = st->s_hi + st->s_lo;
             D += hi - lo == Rp ? __builtin_nan("")
-                               : log1p(-rd.jkw[k] / S) - log1p(-(double)(hi - lo) / (double)Rp);
+                               : log1p(-jkw_own / S) - log1p(-(double)(hi - lo) / (double)Rp);
             st->jk_F[k] = D;
         }
         dF[k] = D;
@@ -2335,8 +2345,9 @@ __device__ void record_run(const RunDesc &rd) {
     double ss[4];  // sums of squared deviations from the means over the n blocks
     for (int q = 0; q < 4; ++q) ss[q] = dsum[2 * q + 1] - dsum[2 * q] * dsum[2 * q] / nbk;
     if (threadIdx.x != 0) return;
+    dd acc = acc_prev;
     if (step > 0) {  // -beta_i F_i = -beta_{i-1} F_{i-1} + ln Q_i, now that step i is complete
-        dd acc = dd_add(dd{st->acc_hi, st->acc_lo}, dd{st->lnq_hi, st->lnq_lo});
+        acc = dd_add(acc_prev, lnq);
         st->acc_hi = acc.hi;
         st->acc_lo = acc.lo;
     }
@@ -2355,14 +2366,14 @@ __device__ void record_run(const RunDesc &rd) {
     o.c_v = beta * beta * (double)varE / (N * R * R);
     o.m = (double)T[2] / (N * R);
     o.chi = beta * (double)varM / (N * R * R);
-    o.ln_Q = step == 0 ? 0.0 : st->lnq_hi + st->lnq_lo;
-    o.minus_beta_F = st->acc_hi + st->acc_lo;
+    o.ln_Q = step == 0 ? 0.0 : lnq.hi + lnq.lo;
+    o.minus_beta_F = acc.hi + acc.lo;
     o.n_families = T[4];
     o.sum_fam2 = T[5];
-    o.sum_cnt2 = step == 0 ? 0 : st->sum_cnt2;
+    o.sum_cnt2 = step == 0 ? 0 : sum_cnt2;
     o.rho_t = (double)T[5] / R;
     o.rho_s = exp(TCL / R);
-    o.rho_t_step = step == 0 ? 0.0 : (double)st->sum_cnt2 / R;
+    o.rho_t_step = step == 0 ? 0.0 : (double)sum_cnt2 / R;
     if (nbk < 2) {
         o.r_eff_E = o.r_eff_absM = o.err_e = o.err_m = o.err_c_v = o.err_chi = __builtin_nan("");
     } else {
@@ -2387,7 +2398,7 @@ __device__ void record_run(const RunDesc &rd) {
     o.jk_cov_c_v = cov ? jfF * dsum[12] : NaN;
     o.jk_cov_chi = cov ? jfF * dsum[13] : NaN;
     rd.records[step] = o;
-    st->r_parents = step == 0 ? 0 : st->R_cur;
+    st->r_parents = step == 0 ? 0 : Rp;
     st->step = step;
     st->cur = nb;
     st->R_cur = Rn;
