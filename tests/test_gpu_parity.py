@@ -140,6 +140,10 @@ CASES = [
     # (the multispin copy's spread network at its deepest shifts)
     (4, 3000, 0, 2, 5.0, "nearest", "msc64"),
     (4, 3000, 0, 2, 5.0, "multinomial", "msc64"),
+    # more than 4096 stretches of 64 parents: the multinomial draws search the
+    # parent blocks' bases and the dense stretch ends instead of the LDS index
+    # of every stretch
+    (4, 300000, 1, 2, 0.6, "multinomial", "msc64"),
     # Poisson resampling: fluctuating R_i, several blocks, strong selection
     (8, 200, 3, 8, 0.44, "poisson", "msc64"),
     (6, 130, 2, 6, 0.6, "poisson", "int8"),
