@@ -252,6 +252,42 @@ def cpu_baseline(betas, energies):
             "host": host_cpu()}
 
 
+def cpu_config3_sample(energies128):
+    """The oracle on a bounded sample of the L=128 workload (R = 100000,
+    nearest-integer resampling, beta 0 -> 1 in 400 steps): sweeps of one
+    64-replica group at beta = 1 (about 5 s) and one nearest-integer
+    resampling of the device run's final population, scaled to a step."""
+    import numpy as np
+    from oracle import pa_oracle as po
+    from workloads import linear_schedule
+    L3, R3, n3 = 128, 100_000, 400
+    betas3 = linear_schedule(1.0, n3)
+    beta = betas3[-1]
+    t4, t8 = po.metropolis_threshold(beta, 4), po.metropolis_threshold(beta, 8)
+    spins = po.init_spins(SEED, L3, 64)
+    t0 = time.perf_counter()
+    sweeps = 0
+    while True:
+        po.sweeps(SEED, L3, spins, n3, 1, t4, t8)
+        sweeps += 1
+        if time.perf_counter() - t0 > 5.0 or sweeps >= 2000:
+            break
+    t_sweep = time.perf_counter() - t0
+    o = po.OracleRun(L3, 4, THETA, SEED, "nearest", betas3)
+    o.R = len(energies128)
+    o.E = np.asarray(energies128, dtype=np.int32)
+    t1 = time.perf_counter()
+    o.copy_counts(betas3[n3 - 1], betas3[n3], n3)
+    t_res = time.perf_counter() - t1
+    step_s = t_sweep / sweeps * THETA * math.ceil(R3 / 64) + t_res
+    return {"workload": "L=128, R=100000, nearest, beta 0->1.0 in 400 steps, theta=10",
+            "value": R3 * L3 * L3 * THETA / step_s / 1e9, "unit": "attempts/ns", "cores": 1,
+            "sample": "%d sweeps of 64 replicas (L=128) at beta=%.1f (%.1f s) and one nearest-integer "
+                      "resampling of %d parents (%.2f s), scaled to a step of R=%d, theta=%d"
+                      % (sweeps, beta, t_sweep, len(energies128), t_res, R3, THETA),
+            "step_seconds": step_s, "resample_s_per_step": t_res}
+
+
 def cpu_config1(pa):
     """The small workload in full on both sides: L=8, R=1000, beta 0 -> 0.44 in
     101 steps, theta=10, nearest-integer resampling.  The oracle's whole run
@@ -371,6 +407,7 @@ def main():
 
     results = {}
     energies_mid = None
+    energies128 = None
     for layout in args.layouts.split(","):
         log("timing layout %s: %d steps" % (layout, K))
         run, wall, prof, recs, attempts = time_layout(pa, torch, betas, layout, K, args.warmup,
@@ -446,6 +483,8 @@ def main():
             "resample_us_per_step": prof["ms_resample"] / n * 1e3, "geometry": prof["geometry"],
             "beta_f_error_per_spin": abs(recs[-1]["minus_beta_F"] - lnz128[-1]) / (128 * 128),
             "final_families": recs[-1]["n_families"], "final_rho_t": recs[-1]["rho_t"]}
+        if not args.no_cpu_baseline:
+            _, _, energies128, _ = run.population(spins=False)
         run.close()
         torch.cuda.empty_cache()
         # the other copy-count rules on the headline workload (same sweeps)
@@ -525,6 +564,9 @@ def main():
             out["cpu_baseline"]["value"] * out["cpu_baseline"]["host"]["usable_cpus"])
         log("timing the small workload in full on the oracle and the device")
         out["cpu_baseline"]["small_workload_in_full"] = cpu_config1(pa)
+        if energies128 is not None:
+            log("timing the CPU oracle sample of the L=128 workload")
+            out["cpu_baseline"]["l128_sample"] = cpu_config3_sample(energies128)
     print(json.dumps(out))
 
 
