@@ -183,6 +183,34 @@ def poisson_uniform(seed: int, step: int, j: int) -> int:
     return int(lib().oracle_poisson_uniform(seed, step, j))
 
 
+def nearest_count(seed: int, step: int, R: int, levels: Dict[int, int], beta_prev: float,
+                  beta_next: float, e_j: int, j: int) -> int:
+    """Copy count of one parent under the nearest-integer rule, for
+    populations too large to resample whole here.
+
+    Parent j (energy e_j) of a population with levels[e] replicas of energy e
+    (R_{i-1} = their sum) at the move beta_prev -> beta_next, dbeta their
+    difference: Q_i = (1/R_{i-1}) sum_e levels[e] exp(-dbeta e) (Eq. Q, the replicas
+    grouped by energy), tau_hat_j = (R / R_{i-1}) exp(-dbeta e_j) / Q_i (Eq.
+    taus), and r_j = floor(tau_hat_j) + [u_j < frac(tau_hat_j)] with u_j the
+    parent's resampling uniform (Eq. resampling-factors).  The rule of
+    OracleRun.copy_counts, one parent at a time.
+    """
+    Rp = sum(levels.values())
+    with mpmath.workprec(PREC_BITS):
+        db = mpmath.mpf(beta_next) - mpmath.mpf(beta_prev)
+        if len(levels) == 1:
+            tau = mpmath.mpf(1)  # one level: every weight equals Q
+        else:
+            Q = mpmath.fsum(n * mpmath.exp(-db * e) for e, n in levels.items()) / Rp
+            tau = mpmath.exp(-db * e_j) / Q
+        tau_hat = mpmath.mpf(R) / Rp * tau
+        _check_margin(mpmath.ldexp(tau_hat, 32), "2^32 tau_hat")
+        fl = mpmath.floor(tau_hat)
+        u = mpmath.ldexp(resample_uniform(seed, step, j), -32)
+        return int(fl) + (1 if u < tau_hat - fl else 0)
+
+
 def poisson_inverse(lam, U: int) -> int:
     """Copies for Poisson resampling by inversion: the smallest k >= 0 with
     U < 2^64 F(k), F(k) = e^-lam sum_{m<=k} lam^m / m! (the Poisson CDF of mean

@@ -472,3 +472,73 @@ def test_l128_nearest_sampled_step_parity(layout):
     lattice fills most of a CU's LDS, so the sweep takes two words per thread)."""
     log("L128 sampled", layout)
     _sampled_step_parity(128, 100_000, "nearest", layout, 400, 1.0, 180, 10, PARITY_SEED, 3)
+
+
+def _check_full_population(run, rec, L, rng, n_samples=8):
+    """Record sums against every replica's E and M, tree order of the family
+    labels and their count, and E, M of sampled stretches of 64 replicas
+    against the oracle's evaluation of their spins."""
+    _, fam, E, M = run.population(spins=False)
+    E64, M64 = E.astype(np.int64), M.astype(np.int64)
+    assert rec["sum_E"] == int(E64.sum()) and rec["sum_E2"] == int((E64 * E64).sum())
+    assert rec["sum_absM"] == int(np.abs(M64).sum()) and rec["sum_M2"] == int((M64 * M64).sum())
+    assert np.all(np.diff(fam) >= 0)  # copies of one parent adjacent, parents ascending
+    assert rec["n_families"] == len(np.unique(fam))
+    for first in rng.choice(rec["R_i"] - 64, n_samples, replace=False):
+        spins, _, Es, Ms = run.population(int(first), 64)
+        Eo, Mo = po.energy_magnetisation(L, spins)
+        assert np.array_equal(Es, Eo) and np.array_equal(Ms, Mo), first
+    return E
+
+
+def test_largest_population_nearest():
+    # R = 2^24, the largest population the boundary accepts, at L = 4: two
+    # steps of nearest-integer resampling with one sweep each.  The copy counts
+    # of 2000 random parents are compared with the oracle's one-parent rule;
+    # the rest holds at any size (count totals, record sums, tree order).
+    L, R, theta = 4, 1 << 24, 1
+    log("largest population, nearest", L, R)
+    betas = linear_schedule(0.5, 2)
+    run = pa.Run(L, R, betas, theta, PARITY_SEED, "nearest", "msc64")
+    rng = np.random.default_rng(5)
+    _, _, E_prev, _ = run.population(spins=False)
+    for i in (1, 2):
+        values, mult = np.unique(E_prev, return_counts=True)
+        levels = {int(e): int(n) for e, n in zip(values, mult)}
+        run.anneal_step()
+        rec = run.observables(i)
+        counts = run.copy_counts()
+        assert len(counts) == len(E_prev)
+        assert int(counts.sum(dtype=np.int64)) == rec["R_i"]
+        assert int((counts.astype(np.int64) ** 2).sum()) == rec["sum_cnt2"]
+        for j in rng.choice(len(E_prev), 2000, replace=False):
+            want = po.nearest_count(PARITY_SEED, i, R, levels, betas[i - 1], betas[i],
+                                    int(E_prev[j]), int(j))
+            assert counts[j] == want, (i, int(j))
+        E_prev = _check_full_population(run, rec, L, rng)
+    run.close()
+
+
+def test_largest_multinomial_population():
+    # R = 2^23 - 1, the largest multinomial population (its quantised weights
+    # total below 2^63), at L = 4.  The first step has dbeta = 0: every weight
+    # is 2^40, so the draws' total W = R 2^40 is the largest the kernels meet,
+    # and the copy counts are multinomial with equal probabilities, whose share
+    # of childless parents is (1 - 1/R)^R (within six standard deviations).
+    L, R = 4, (1 << 23) - 1
+    log("largest population, multinomial", L, R)
+    betas = [0.0, 0.0, 0.3]
+    run = pa.Run(L, R, betas, 1, PARITY_SEED, "multinomial", "msc64")
+    rng = np.random.default_rng(6)
+    for i in (1, 2):
+        run.anneal_step()
+        rec = run.observables(i)
+        counts = run.copy_counts()
+        assert rec["R_i"] == R and int(counts.sum(dtype=np.int64)) == R
+        assert int((counts.astype(np.int64) ** 2).sum()) == rec["sum_cnt2"]
+        if i == 1:
+            p0 = (1.0 - 1.0 / R) ** R
+            assert abs(float(np.mean(counts == 0)) - p0) < 6.0 * math.sqrt(p0 * (1 - p0) / R)
+            assert rec["ln_Q"] == 0.0
+        _check_full_population(run, rec, L, rng)
+    run.close()

@@ -109,3 +109,20 @@ def test_counts_depend_only_on_energy_level_and_uniform():
         fl = math.floor(tau[j])
         if abs((tau[j] - fl) - u) > 1e-9:
             assert c[j] == fl + (1 if u < tau[j] - fl else 0)
+
+
+@pytest.mark.parametrize("beta_prev,beta_next", [(0.0, 0.37), (0.2, 0.2), (0.31, 0.9)])
+def test_one_parent_nearest_count_matches_the_whole_population_rule(beta_prev, beta_next):
+    # nearest_count (one parent, from the level counts) against copy_counts
+    # (every parent, replica by replica) on the same population and uniforms;
+    # the second case is a zero step, whose counts are all one
+    o = _population(L=6, R=300, seed=11, theta=2)
+    counts, _ = o.copy_counts(beta_prev, beta_next, 3)
+    values, mult = np.unique(o.E, return_counts=True)
+    levels = {int(e): int(n) for e, n in zip(values, mult)}
+    got = [po.nearest_count(o.seed, 3, o.R, levels, beta_prev, beta_next, int(o.E[j]), j)
+           for j in range(len(o.E))]
+    assert np.array_equal(np.array(got, dtype=np.int32), counts)
+    # a population on a single level: tau_hat = R / R_{i-1} whatever dbeta is
+    one = {-72: 40}
+    assert all(po.nearest_count(7, 2, 40, one, 0.1, 0.5, -72, j) == 1 for j in range(40))
