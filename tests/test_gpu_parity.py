@@ -140,6 +140,10 @@ CASES = [
     # (the multispin copy's spread network at its deepest shifts)
     (4, 3000, 0, 2, 5.0, "nearest", "msc64"),
     (4, 3000, 0, 2, 5.0, "multinomial", "msc64"),
+    # a thousand sweeps per step: half-sweep counters h = 2 (theta (i - 1) + s)
+    # + colour up to 6000, in both layouts
+    (4, 130, 1000, 3, 0.44, "nearest", "msc64"),
+    (4, 130, 1000, 3, 0.44, "multinomial", "int8"),
     # more than 4096 stretches of 64 parents: the multinomial draws search the
     # parent blocks' bases and the dense stretch ends instead of the LDS index
     # of every stretch
