@@ -458,7 +458,9 @@ pa_status engine_create(pa_batch *B, const pa_config *cfgs, int n, void *ws, siz
     lc.any_nearest = lc.any_multi = lc.any_poisson = false;
     lc.any_msc = lc.any_int8 = false;
     lc.any_update[0] = lc.any_update[1] = false;
+    lc.max_L = 0;
     for (int r = 0; r < n; ++r) {
+        lc.max_L = std::max(lc.max_L, (int)cfgs[r].L);
         if (cfgs[r].resample == PA_RESAMPLE_MULTINOMIAL) lc.any_multi = true;
         else if (cfgs[r].resample == PA_RESAMPLE_POISSON) lc.any_poisson = true;
         else lc.any_nearest = true;

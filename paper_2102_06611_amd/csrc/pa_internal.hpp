@@ -43,6 +43,7 @@ struct LaunchCtx {
     bool any_update[2];      // spin-update rules present in the batch (PA_UPDATE_*)
     bool count_calls = false;  // sweeps count the Philox calls the words need (pa_profile 3)
     int max_nblk = 1;          // most slot blocks of a multinomial run (LDS of its draws)
+    int max_L = 0;             // largest lattice side of the batch
 };
 
 void set_last_error(const char *msg);  // for pa_last_error(NULL)

@@ -188,8 +188,7 @@ constexpr double kPoissonMaxMean = 65536.0;  // largest supported tau_hat
 constexpr int kPoissonMax = 1 << 18;          // > kPoissonMaxMean + 40 sqrt(kPoissonMaxMean)
 constexpr double kPoissonMargin = 0x1p-8;     // in units of U
 
-__global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
-    const RunDesc &rd = runs[blockIdx.x];
+__device__ void norm_run(const RunDesc &rd) {
     RunState *st = rd.st;
     __shared__ double sh_hi[4], sh_lo[4];
     __shared__ int amb_any, ok;
@@ -344,6 +343,8 @@ __global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) {
         st->err_step = i;
     }
 }
+
+__global__ void __launch_bounds__(256) k_norm(const RunDesc *runs) { norm_run(runs[blockIdx.x]); }
 
 // ------------------------------------------------------------------ free-energy jackknife
 
@@ -565,6 +566,95 @@ __global__ void __launch_bounds__(256) k_multi_weights(const RunDesc *runs, Work
     for (int m = 0; m < 4; ++m) {
         if (j + m < Rp) {
             q[m] = rd.zlev[((e[m] + 2 * rd.N) >> 2) - kmin];
+            rd.cnt[j + m] = 0;
+        }
+    }
+    int64_t tot;
+    uint64_t run = (uint64_t)block_exclusive_scan((int64_t)(q[0] + q[1] + q[2] + q[3]), sh, &tot);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        run += q[m];
+        if (j + m < Rp) {
+            rd.cum[j + m] = run;
+            if (((j + m) & 7) == 7 || j + m == Rp - 1) rd.e8[(j + m) >> 3] = run;
+            if (((j + m) & 63) == 63 || j + m == Rp - 1) rd.send[(j + m) >> 6] = run;
+        }
+    }
+    if (threadIdx.x == 0) {
+        rd.part[b * 8 + 3] = tot;
+        rd.part[b * 8 + 0] = 0;
+    }
+}
+
+// Multinomial, pass 1 with the step's normalisation in the same launch, for
+// batches whose runs all resample multinomially at L <= 64: one extra block
+// per run does the whole of k_norm (thresholds, S, ln Q's inputs, the checks
+// that end a run), while every block of parents forms the quantised level
+// weights it needs itself in LDS, with k_norm's operations in k_norm's order
+// (so the integers are the same), and then proceeds as k_multi_weights.  A
+// step that k_norm stops (no further temperature, a bad schedule, an
+// undecidable weight) is recognised by every block on its own, and leaves
+// the previous step's counts untouched.
+constexpr int kFusedMaxLevels = 64 * 64 + 1;
+__global__ void __launch_bounds__(256) k_multi_norm_weights(const RunDesc *runs, WorkMap map,
+                                                            int slot_blocks) {
+    if ((int)blockIdx.x >= slot_blocks) {
+        norm_run(runs[(int)blockIdx.x - slot_blocks]);
+        return;
+    }
+    int b;
+    const RunDesc &rd = runs[map_block(map, blockIdx.x, &b)];
+    RunState *st = rd.st;
+    __shared__ uint64_t zl[kFusedMaxLevels];
+    __shared__ double sh_hi[2], sh_lo[2];
+    __shared__ int64_t sh[32];
+    __shared__ int amb_any;
+    const int j = b * kSlotBlock + 4 * (int)threadIdx.x;
+    int32_t e[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (j + m < rd.C) e[m] = rd.E[j + m];
+    if (st->err || rd.resample != PA_RESAMPLE_MULTINOMIAL) return;
+    const int i = st->step + 1;
+    if (i > rd.max_steps) return;
+    const double b0 = rd.betas[i - 1], b1 = rd.betas[i];
+    if (!(b1 >= b0) || !(b1 <= 1e300)) return;
+    const int Rp = st->R_cur, kmin = st->kmin, kmax = st->kmax;
+    const int nlev = kmax - kmin + 1;
+    const dd db = two_sum(b1, -b0);
+    const bool exact = (db.hi == 0.0) || (nlev == 1);
+    if (threadIdx.x == 0) amb_any = 0;
+    // k_norm's level weights: thread t's first w_t = e^{-4 dbeta t} (w_0 = 1),
+    // then products with e^{-4 dbeta blockDim} = w_1 w_{blockDim-1}
+    dd w{1.0, 0.0};
+    if (threadIdx.x != 0 && !exact) dd_exp_neg(dd_mul_d(db, 4.0 * threadIdx.x), &w);
+    dd stride{1.0, 0.0};
+    if (!exact && nlev > (int)blockDim.x) {
+        if (threadIdx.x == 1 || threadIdx.x == blockDim.x - 1) {
+            sh_hi[threadIdx.x == 1 ? 0 : 1] = w.hi;
+            sh_lo[threadIdx.x == 1 ? 0 : 1] = w.lo;
+        }
+        __syncthreads();
+        stride = dd_mul(dd{sh_hi[0], sh_lo[0]}, dd{sh_hi[1], sh_lo[1]});
+    }
+    bool amb = false;
+    for (int l = threadIdx.x; l < nlev; l += blockDim.x) {
+        uint64_t z;
+        if (exact || l == 0)
+            z = 1ull << 40;
+        else
+            z = (w.hi == 0.0) ? 0ull : dd_floor_decided(dd_ldexp(w, 40), &amb);
+        zl[l] = z;
+        if (!exact) w = dd_mul(w, stride);
+    }
+    if (amb) atomicOr(&amb_any, 1);
+    __syncthreads();
+    if (amb_any) return;  // k_norm's block reports the step as undecidable
+    uint64_t q[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (j + m < Rp) {
+            q[m] = zl[((e[m] + 2 * rd.N) >> 2) - kmin];
             rd.cnt[j + m] = 0;
         }
     }
@@ -2875,15 +2965,21 @@ hipError_t launch_weighted(const LaunchCtx &c, int first, int count, pa_weighted
 }
 
 hipError_t launch_counts(const LaunchCtx &c) {
-    PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
+    // multinomial-only batches at L <= 64 fold the normalisation into the weights' launch
+    const bool fused = c.any_multi && !c.any_nearest && !c.any_poisson && c.max_L <= 64;
+    if (!fused) PA_LAUNCH(k_norm, dim3(c.n_runs), dim3(256), 0, c.stream, c.runs);
     if (c.any_nearest)
         PA_LAUNCH(k_counts_nearest, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
                   c.slots.map);
     if (c.any_poisson)
         PA_LAUNCH(k_counts_poisson, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs, c.slots.map);
     if (c.any_multi) {
-        PA_LAUNCH(k_multi_weights, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
-                  c.slots.map);
+        if (fused)
+            PA_LAUNCH(k_multi_norm_weights, dim3(c.slots.total + c.n_runs), dim3(256), 0, c.stream,
+                      c.runs, c.slots.map, c.slots.total);
+        else
+            PA_LAUNCH(k_multi_weights, dim3(c.slots.total), dim3(256), 0, c.stream, c.runs,
+                      c.slots.map);
         PA_LAUNCH(k_multi_draw, dim3(c.slots.total), dim3(kSlotBlock), draw_lds_bytes(c.max_nblk),
                   c.stream, c.runs, c.slots.map);
     }
