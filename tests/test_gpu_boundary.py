@@ -151,3 +151,33 @@ def test_single_run_free_energy_jackknife_matches_spread_over_runs(L, R, beta_f,
         sd = math.sqrt(w[i]["var_beta_F"]) * np.std([b.observables(k, i)["e"] for k in range(64)])
         assert abs(cj.mean() - w[i]["cov_e"]) < 3 * sd / math.sqrt(63) + 3 * cj.std() / 8
     b.close()
+
+
+@pytest.mark.parametrize("resample", ["nearest", "multinomial"])
+def test_lower_temperature_stops_the_run_on_the_device(resample):
+    # A caller-chosen step to a lower beta is refused by the step's
+    # normalisation on the device (sticky PA_ERR_ARG).  The population, its
+    # records and the copy counts stay those of the last good step, whichever
+    # kernels normalise (multinomial runs at L <= 64 fold it into the weights).
+    run = pa.Run(8, 300, None, 2, 17, resample, "msc64", n_steps=6)
+    for b in (0.1, 0.2):
+        run.anneal_step_to(b)
+    run.sync()
+    step, R_i = run.current()
+    spins, fam, E, M = run.population()
+    counts = run.copy_counts()
+    rec = run.observables(step)
+    run.anneal_step_to(0.15)
+    with pytest.raises(pa.PAError) as ei:
+        run.sync()
+    assert ei.value.status == pa.PA_ERR_ARG
+    assert run.current() == (step, R_i)
+    s2, f2, E2, M2 = run.population()
+    assert np.array_equal(s2, spins) and np.array_equal(f2, fam)
+    assert np.array_equal(E2, E) and np.array_equal(M2, M)
+    assert np.array_equal(run.copy_counts(), counts)
+    assert run.observables(step) == rec
+    with pytest.raises(pa.PAError) as ei:
+        run.observables(step + 1)
+    assert ei.value.status == pa.PA_ERR_ARG
+    run.close()
