@@ -56,6 +56,13 @@ void oracle_philox4x32_10(uint32_t key0, uint32_t key1, const uint32_t ctr[4], u
     out[3] = c[3];
 }
 
+/* The same generator over n counters (ctr and out hold 4n words each), for
+ * comparisons over many counters without a call per counter. */
+void oracle_philox4x32_10_n(uint32_t key0, uint32_t key1, int64_t n, const uint32_t *ctr,
+                            uint32_t *out) {
+    for (int64_t i = 0; i < n; ++i) oracle_philox4x32_10(key0, key1, ctr + 4 * i, out + 4 * i);
+}
+
 /* ---------------- random streams ----------------
  * key = (seed mod 2^32, seed div 2^32).  The fourth counter word carries a
  * stream tag in its top nibble.  Replica slot r belongs to group g = r / 64

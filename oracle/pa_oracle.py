@@ -99,6 +99,8 @@ def lib():
         p_i32 = ctypes.POINTER(ctypes.c_int32)
         L.oracle_philox4x32_10.argtypes = [u32, u32, p_u32, p_u32]
         L.oracle_philox4x32_10.restype = None
+        L.oracle_philox4x32_10_n.argtypes = [u32, u32, ctypes.c_int64, p_u32, p_u32]
+        L.oracle_philox4x32_10_n.restype = None
         L.oracle_sweep_top6.argtypes = [u64, u32, u32, u32, u32]
         L.oracle_sweep_top6.restype = u32
         L.oracle_word_uniforms.argtypes = [u64, u32, u32, u32, ctypes.POINTER(ctypes.c_uint64),
@@ -139,6 +141,15 @@ def philox4x32_10(key: int, ctr) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     lib().oracle_philox4x32_10(key & 0xFFFFFFFF, key >> 32, _ptr(c, ctypes.c_uint32),
                                _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def philox4x32_10_many(key: int, ctrs) -> np.ndarray:
+    """Philox4x32-10 of every row of an [n, 4] array of counters under one key."""
+    c = np.ascontiguousarray(np.asarray(ctrs, dtype=np.uint32).reshape(-1, 4))
+    out = np.zeros_like(c)
+    lib().oracle_philox4x32_10_n(key & 0xFFFFFFFF, key >> 32, len(c), _ptr(c, ctypes.c_uint32),
+                                 _ptr(out, ctypes.c_uint32))
     return out
 
 

@@ -16,6 +16,8 @@
 #include <string.h>
 
 void oracle_philox4x32_10(uint32_t key0, uint32_t key1, const uint32_t ctr[4], uint32_t out[4]);
+void oracle_philox4x32_10_n(uint32_t key0, uint32_t key1, int64_t n, const uint32_t *ctr,
+                            uint32_t *out);
 uint32_t oracle_sweep_top6(uint64_t seed, uint32_t w, uint32_t g, uint32_t h, uint32_t lane);
 void oracle_word_uniforms(uint64_t seed, uint32_t w, uint32_t g, uint32_t h, const uint64_t thr[64],
                           const int needs[64], uint32_t u[64]);
@@ -63,6 +65,16 @@ static void rng_streams(void) {
             oracle_philox4x32_10(keys[k][0], keys[k][1], ctrs[c], out);
             mix(out, sizeof out);
         }
+    /* the batched form over 0, 1 and 5 counters, each buffer exactly 4n words */
+    for (int64_t n = 0; n <= 5; n += n ? 4 : 1) {
+        uint32_t *ctr = (uint32_t *)exact_alloc((size_t)(4 * n) * sizeof(uint32_t));
+        uint32_t *out = (uint32_t *)exact_alloc((size_t)(4 * n) * sizeof(uint32_t));
+        for (int64_t i = 0; i < 4 * n; ++i) ctr[i] = (uint32_t)(0x9E3779B9u * (uint32_t)(i + 1));
+        oracle_philox4x32_10_n(keys[2][0], keys[2][1], n, ctr, out);
+        mix(out, (size_t)(4 * n) * sizeof(uint32_t));
+        free(ctr);
+        free(out);
+    }
     const uint64_t seeds[3] = {0ull, 12345ull, 0xFFFFFFFFFFFFFFFFull};
     for (int s = 0; s < 3; ++s)
         for (uint32_t j = 0; j < 70; ++j) {

@@ -45,6 +45,14 @@ def test_philox_matches_rocrand(rocrand_ref):
     assert len(ref) == len(queries)
     for (seed, ctr), r in zip(queries, ref):
         assert list(po.philox4x32_10(seed, ctr)) == r, (seed, ctr)
+    # the batched form, one key over many counters
+    for seed in (0, 12345, 2 ** 64 - 1):
+        idx = [i for i, (s, _) in enumerate(queries) if s == seed]
+        ctrs = np.array([queries[i][1] for i in idx], dtype=np.uint32)
+        got = po.philox4x32_10_many(seed, ctrs)
+        assert got.shape == (len(idx), 4)
+        assert [list(map(int, g)) for g in got] == [ref[i] for i in idx]
+    assert po.philox4x32_10_many(7, np.zeros((0, 4), dtype=np.uint32)).shape == (0, 4)
 
 
 def test_sweep_uniform_top_bits_and_ties_follow_the_stream_map():
