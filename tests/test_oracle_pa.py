@@ -1,7 +1,9 @@
 """Pins for whole oracle runs (no GPU): free energy, energy and specific heat
 against the exact L = 4 results, family statistics on hand-built populations,
 and the invariants the method guarantees."""
+import concurrent.futures
 import math
+import multiprocessing
 
 import mpmath
 import numpy as np
@@ -107,6 +109,36 @@ def test_free_energy_energy_and_specific_heat_match_exact_L4():
     cv_ex = float(exact.specific_heat(L, betas[-1]))
     assert abs(np.mean(e_end) - e_ex) < 0.02
     assert abs(np.mean(cv_end) - cv_ex) < 0.1 * cv_ex
+
+
+L8_BETAS = linear_schedule(0.44, 30)
+
+
+def _l8_run(seed):
+    o = po.run(8, 2000, L8_BETAS, 4, seed, "nearest")
+    return [(r.minus_beta_F, r.e, r.c_v) for r in o.records]
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(300)
+def test_free_energy_energy_and_specific_heat_match_exact_L8():
+    """The same at L = 8, where the periodic neighbours of a site are four
+    distinct sites (at L = 4 the two neighbours two steps away coincide, which
+    can hide a wrapped index); eight runs of R = 2000, beta 0 -> 0.44 in 30
+    steps, theta = 4, compared half-way and at the end."""
+    po.build()
+    seeds = list(range(201, 209))
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=8, mp_context=ctx) as ex:
+        res = list(ex.map(_l8_run, seeds))
+    for i in (15, 30):
+        beta = L8_BETAS[i]
+        exact_vals = (float(exact.ln_z_kaufman(8, beta)), float(exact.energy_per_spin(8, beta)),
+                      float(exact.specific_heat(8, beta)))
+        for k, (want, floor) in enumerate(zip(exact_vals, (0.01, 0.002, 0.005))):
+            got = np.array([r[i][k] for r in res])
+            se = got.std(ddof=1) / math.sqrt(len(got))
+            assert abs(got.mean() - want) < 5 * se + floor, (i, k, got.mean(), want, se)
 
 
 def test_overlap_matches_gaussian_closed_form_and_paper_values(golden_dir):
