@@ -456,11 +456,12 @@ def _sampled_step_parity(L, R, resample, layout, n_steps, beta_f, k, theta, seed
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("layout", ["msc64", "int8"])
-def test_l64_multinomial_sampled_step_parity(layout):
-    """L=64, R=100000, multinomial, beta 0 -> 0.4407 in 200 steps: step 120 -> 121."""
-    log("L64 sampled", layout)
-    _sampled_step_parity(64, 100_000, "multinomial", layout, 200, 0.4407, 120, 10, PARITY_SEED)
+@pytest.mark.parametrize("layout,k", [("msc64", 120), ("int8", 120), ("msc64", 199)])
+def test_l64_multinomial_sampled_step_parity(layout, k):
+    """L=64, R=100000, multinomial, beta 0 -> 0.4407 in 200 steps: step k -> k + 1
+    (k = 199: the last step, into beta_c, where few families are left)."""
+    log("L64 sampled", layout, k)
+    _sampled_step_parity(64, 100_000, "multinomial", layout, 200, 0.4407, k, 10, PARITY_SEED)
 
 
 @pytest.mark.slow
