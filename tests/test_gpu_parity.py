@@ -465,21 +465,26 @@ def test_l64_multinomial_sampled_step_parity(layout, k):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("L,k,layout", [(64, 120, "msc64"), (128, 180, "msc64"), (128, 180, "int8")])
-def test_heatbath_sampled_step_parity(L, k, layout):
-    """Heatbath at full size: L=64 (one group per block, one word per thread)
-    and L=128 (two words per thread, both layouts), R=100000, nearest."""
-    log("heatbath sampled", L, layout)
+@pytest.mark.parametrize("L,k,layout,resample", [(64, 120, "msc64", "nearest"),
+                                                (64, 150, "msc64", "multinomial"),
+                                                (128, 180, "msc64", "nearest"),
+                                                (128, 180, "int8", "nearest")])
+def test_heatbath_sampled_step_parity(L, k, layout, resample):
+    """Heatbath at full size: L=64 (one group per block, one word per thread;
+    nearest and multinomial copies) and L=128 (two words per thread, both
+    layouts), R=100000."""
+    log("heatbath sampled", L, layout, resample)
     n, bf = (200, 0.4407) if L == 64 else (400, 1.0)
-    _sampled_step_parity(L, 100_000, "nearest", layout, n, bf, k, 10, PARITY_SEED, 3,
+    _sampled_step_parity(L, 100_000, resample, layout, n, bf, k, 10, PARITY_SEED, 3,
                          update="heatbath")
 
 
 @pytest.mark.slow
-def test_l64_poisson_sampled_step_parity():
+@pytest.mark.parametrize("layout", ["msc64", "int8"])
+def test_l64_poisson_sampled_step_parity(layout):
     """L=64, R=100000, Poisson, beta 0 -> 0.4407 in 200 steps: step 120 -> 121."""
-    log("L64 sampled poisson")
-    _sampled_step_parity(64, 100_000, "poisson", "msc64", 200, 0.4407, 120, 10, PARITY_SEED)
+    log("L64 sampled poisson", layout)
+    _sampled_step_parity(64, 100_000, "poisson", layout, 200, 0.4407, 120, 10, PARITY_SEED)
 
 
 @pytest.mark.slow
