@@ -1778,18 +1778,33 @@ __device__ __forceinline__ void ripple(uint32_t (&P)[K], uint32_t c, int from) {
     }
 }
 
-// Butterfly over the 64 lanes: after it every lane holds the sum of all
-// lanes' K-plane counters (one 32-bit half) in K + 6 planes; returns bit
-// `sh` of that sum, i.e. the count of replica sh of this half.
+// Sum over the wavefront of a K-plane counter pair (lo: replicas 0..31, hi:
+// replicas 32..63), as a reduce-scatter: the first exchange, between lanes 32
+// apart, hands each lane its partner's copy of the half it keeps (lanes 0..31
+// the low half, lanes 32..63 the high one), so the five butterfly levels that
+// follow add one 32-bit half per lane instead of two.  After them every lane of
+// a 32-lane group holds its half's sum over all 64 lanes in K + 6 planes;
+// returns bit lane mod 32 of it, the count of replica `lane`.
 template <int K>
-__device__ __forceinline__ int wave_count_half(const uint32_t (&p)[K], int sh) {
+__device__ __forceinline__ int wave_count(const uint32_t (&lo)[K], const uint32_t (&hi)[K], int lane) {
+    const bool upper = lane >= 32;
     uint32_t a[K + 6];
+    uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < K + 6; ++k) a[k] = k < K ? p[k] : 0u;
+    for (int k = 0; k < K; ++k) {
+        const uint32_t mine = upper ? hi[k] : lo[k];
+        const uint32_t b = __shfl_xor(upper ? lo[k] : hi[k], 32, 64);
+        const uint32_t sum = mine ^ b ^ c;
+        c = maj3(mine, b, c);
+        a[k] = sum;
+    }
+    a[K] = c;
 #pragma unroll
-    for (int lev = 0; lev < 6; ++lev) {
+    for (int k = K + 1; k < K + 6; ++k) a[k] = 0u;
+#pragma unroll
+    for (int lev = 1; lev < 6; ++lev) {
         const int off = 32 >> lev;
-        uint32_t c = 0;
+        c = 0;
 #pragma unroll
         for (int k = 0; k < K + lev; ++k) {
             const uint32_t b = __shfl_xor(a[k], off, 64);
@@ -1799,6 +1814,7 @@ __device__ __forceinline__ int wave_count_half(const uint32_t (&p)[K], int sh) {
         }
         a[K + lev] = c;
     }
+    const int sh = lane & 31;
     int n = 0;
 #pragma unroll
     for (int k = 0; k < K + 6; ++k) n |= (int)((a[k] >> sh) & 1u) << k;
@@ -1820,11 +1836,8 @@ struct MeasCounters {
         ripple(mh, (uint32_t)(s >> 32), 0);
     }
     __device__ __forceinline__ void wave_totals(int lane, int *U, int *up) const {
-        const int sh = lane & 31;
-        const int u_lo = wave_count_half<kPlanesU>(ul, sh), u_hi = wave_count_half<kPlanesU>(uh, sh);
-        const int m_lo = wave_count_half<kPlanesM>(ml, sh), m_hi = wave_count_half<kPlanesM>(mh, sh);
-        *U = lane < 32 ? u_lo : u_hi;
-        *up = lane < 32 ? m_lo : m_hi;
+        *U = wave_count<kPlanesU>(ul, uh, lane);
+        *up = wave_count<kPlanesM>(ml, mh, lane);
     }
 };
 
