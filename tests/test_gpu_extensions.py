@@ -424,6 +424,48 @@ def test_effective_population_size_is_bounded_below_by_the_families():
         assert o["err_e"] > 0.0 and o["err_c_v"] > 0.0
 
 
+def test_blocked_error_bar_of_e_matches_the_spread_of_independent_runs():
+    """Sec. "Statistical errors" (the comparison of its error-bar figure): at
+    L = 32, R = 50000, theta = 10, dbeta = 0.01 the single-run error bar of e
+    from the blocking analysis agrees with the standard deviation of e over
+    independent runs (64 runs here; the standard deviation of 64 values has a
+    relative standard error of 9 %)."""
+    betas = linear_schedule(0.44, 44)
+    specs = [dict(L=32, R=50000, theta=10, seed=1000 + s, betas=betas, resample="nearest")
+             for s in range(64)]
+    b = pa.Batch(specs)
+    b.run(44)
+    for i in (10, 25, 35, 44):
+        e = np.array([b.observables(k, i)["e"] for k in range(64)])
+        err = np.array([b.observables(k, i)["err_e"] for k in range(64)])
+        ratio = err.mean() / e.std(ddof=1)
+        log("step", i, "mean err_e / std e", ratio)
+        assert 0.7 < ratio < 1.4, (i, ratio)
+    b.close()
+
+
+def test_effective_population_size_near_criticality():
+    """Sec. "Statistical errors": with one sweep per step the population near
+    criticality is strongly correlated; the paper finds R_eff of about 600 for
+    R = 50000 (L = 32).  Here dbeta = 0.01 up to beta = 0.44 with
+    checkerboard instead of sequential updates: the mean R_eff(E) over three
+    seeds at beta = 0.44 is required within a factor 2.5 of 600, and ten sweeps
+    per step keep it at least twenty times larger."""
+    betas = linear_schedule(0.44, 44)
+    reff = {}
+    for theta in (1, 10):
+        vals = []
+        for seed in (11, 12, 13):
+            r = pa.Run(32, 50000, betas, theta, seed, "nearest", "msc64")
+            r.run(44)
+            vals.append(r.observables(44)["r_eff_E"])
+            r.close()
+        reff[theta] = float(np.mean(vals))
+        log("theta", theta, "R_eff(E) at beta 0.44", vals)
+    assert 600 / 2.5 < reff[1] < 600 * 2.5, reff
+    assert reff[10] > 20 * reff[1], reff
+
+
 def test_autotuner_times_candidates_and_keeps_results():
     from paper_2102_06611_amd import autotune
     betas = linear_schedule(0.44, 10)
