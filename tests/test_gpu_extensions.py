@@ -214,6 +214,23 @@ def test_overlap_matches_oracle(dbeta):
     run.close()
 
 
+def test_histogram_overlap_at_the_critical_point():
+    """Sec. "Bias with resampling": for L = 32 at beta_c the overlap of the
+    energy histograms at beta_c and beta_c + dbeta is about 0.3 for dbeta =
+    0.02 and below 10 % for dbeta >= 0.05, decaying away from dbeta = 0.  A
+    population at beta_c (R = 100000, theta = 10, dbeta = 0.01 steps) is required
+    to give 0.3 within 50 % and less than 0.1 at 0.05, decreasing in dbeta."""
+    betas = linear_schedule(0.4407, 44)
+    run = pa.Run(32, 100000, betas, 10, 77, "nearest", "msc64")
+    run.run(44)
+    a = {d: run.overlap(d) for d in (0.005, 0.01, 0.02, 0.05, 0.1)}
+    run.close()
+    log("overlap at beta_c", a)
+    assert 0.15 < a[0.02] < 0.45, a
+    assert a[0.05] < 0.1, a
+    assert a[0.005] > a[0.01] > a[0.02] > a[0.05] > a[0.1], a
+
+
 def test_adaptive_dbeta_hits_the_target_overlap():
     run, E, _ = _population_after(16, 3000, 10)
     for target in (0.7, 0.85, 0.95):
