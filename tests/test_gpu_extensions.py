@@ -483,6 +483,40 @@ def test_effective_population_size_near_criticality():
     assert reff[10] > 20 * reff[1], reff
 
 
+def _tau_eff(bf, n, thetas, R=128000, seeds=(5, 6)):
+    """Fit of Eq. Reff, R_eff / R = 1 - c exp(-theta / tau_eff), to R_eff(E) / R
+    averaged over the last five steps of runs at L = 64 with dbeta = 0.005
+    (points with R_eff / R >= 0.97 carry no information on the decay)."""
+    ys = []
+    for th in thetas:
+        vals = []
+        for seed in seeds:
+            r = pa.Run(64, R, linear_schedule(bf, n), th, seed, "nearest", "msc64")
+            r.run(n)
+            vals += [r.observables(i)["r_eff_E"] / r.observables(i)["R_i"] for i in range(n - 4, n + 1)]
+            r.close()
+        ys.append(float(np.mean(vals)))
+    th, y = np.array(thetas, dtype=float), np.array(ys)
+    ok = y < 0.97
+    slope = np.polyfit(th[ok], np.log(1.0 - y[ok]), 1)[0]
+    log("beta_f", bf, "R_eff/R", dict(zip(thetas, ys)), "tau_eff", -1.0 / slope)
+    return -1.0 / slope
+
+
+@pytest.mark.slow
+def test_theta_dependence_of_the_effective_population_size():
+    """Sec. "Statistical errors", Eq. Reff: at L = 64, dbeta = 0.005 and R =
+    128000 the paper fits tau_eff = 2.2 at T = 2.5 and 51.2 at T = 2.325.  These
+    checkerboard runs (nearest-integer copies, 100 blocks) are required to give
+    tau_eff within a factor 2 of 2.2 at T = 2.5 and within a factor 2.5 of 51.2
+    at T = 2.325, the latter at least five times the former."""
+    t_hot = _tau_eff(0.4, 80, (1, 2, 3, 4, 6, 8))
+    t_crit = _tau_eff(1.0 / 2.325, 86, (5, 10, 20, 40, 80))
+    assert 2.2 / 2 < t_hot < 2.2 * 2, t_hot
+    assert 51.2 / 2.5 < t_crit < 51.2 * 2.5, t_crit
+    assert t_crit > 5 * t_hot, (t_hot, t_crit)
+
+
 def test_autotuner_times_candidates_and_keeps_results():
     from paper_2102_06611_amd import autotune
     betas = linear_schedule(0.44, 10)
