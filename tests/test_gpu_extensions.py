@@ -517,6 +517,41 @@ def test_theta_dependence_of_the_effective_population_size():
     assert t_crit > 5 * t_hot, (t_hot, t_crit)
 
 
+@pytest.mark.slow
+def test_energy_relaxation_time_without_resampling():
+    """Sec. "Bias", behaviour without resampling: at L = 32, R = 10000, with
+    resampling off and steps of dbeta = 0.1 to beta_c, the relative deviation of
+    the energy from Kaufman's, averaged over 200 runs, follows
+    eps = a exp(-theta / tau_rel) (1 + b / theta) with tau_rel = 45.4(6).  Here
+    256 runs per theta, the steps 0, 0.1, 0.2, 0.3, 0.4, beta_c; the fitted
+    tau_rel is required within 25 % of 45.4 and |eps| to fall with theta."""
+    from scipy.optimize import curve_fit
+    from oracle import exact
+    bc = 0.5 * math.log(1.0 + math.sqrt(2.0))
+    betas = np.array([0.0, 0.1, 0.2, 0.3, 0.4, bc])
+    e_ex = float(exact.energy_per_spin(32, bc))
+    thetas = [1, 2, 5, 10, 20, 40, 60, 80, 120, 160, 200]
+    eps, se = [], []
+    for th in thetas:
+        es = []
+        for chunk in range(4):
+            specs = [dict(L=32, R=10000, theta=th, seed=5000 + 64 * chunk + k, betas=betas,
+                          resample="none") for k in range(64)]
+            b = pa.Batch(specs)
+            b.run(5)
+            es += [b.observables(k, 5)["e"] for k in range(64)]
+            b.close()
+        es = np.array(es)
+        eps.append((es.mean() - e_ex) / e_ex)
+        se.append(es.std(ddof=1) / math.sqrt(len(es)) / abs(e_ex))
+    th, y = np.array(thetas, dtype=float), np.array(eps)
+    fit = lambda t, a, tau, b: a * np.exp(-t / tau) * (1.0 + b / t)
+    p, _ = curve_fit(fit, th, y, p0=(y[3], 40.0, 1.0), sigma=np.array(se), maxfev=20000)
+    log("eps", dict(zip(thetas, eps)), "tau_rel", p[1])
+    assert np.all(np.diff(np.abs(y)) < 0), y
+    assert 45.4 * 0.75 < p[1] < 45.4 * 1.25, p
+
+
 def test_autotuner_times_candidates_and_keeps_results():
     from paper_2102_06611_amd import autotune
     betas = linear_schedule(0.44, 10)
