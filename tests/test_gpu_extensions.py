@@ -552,6 +552,30 @@ def test_energy_relaxation_time_without_resampling():
     assert 45.4 * 0.75 < p[1] < 45.4 * 1.25, p
 
 
+def test_error_bars_fall_as_one_over_sqrt_population():
+    """Sec. "Statistical errors": with theta = 10 the population stays close to
+    equilibrium and the statistical error of the energy falls as 1 / sqrt(R).
+    L = 32, dbeta = 0.01 to beta = 0.44, R = 12500, 50000 and 200000 (the
+    blocked error bar err_e of each run, averaged over four seeds and over the
+    steps to beta = 0.3, 0.4 and 0.44): err_e sqrt(R) is required to agree
+    within 25 % across the three sizes."""
+    betas = linear_schedule(0.44, 44)
+    steps = (30, 40, 44)
+    scaled = {}
+    for R in (12500, 50000, 200000):
+        specs = [dict(L=32, R=R, theta=10, seed=300 + s, betas=betas, resample="nearest")
+                 for s in range(4)]
+        b = pa.Batch(specs)
+        b.run(44)
+        scaled[R] = np.array([[b.observables(k, i)["err_e"] for k in range(4)] for i in steps]
+                             ).mean(axis=1) * math.sqrt(R)
+        b.close()
+    log("err_e sqrt(R) at steps", steps, scaled)
+    ref = scaled[50000]
+    for R in (12500, 200000):
+        assert np.all(np.abs(scaled[R] / ref - 1.0) < 0.25), scaled
+
+
 def test_autotuner_times_candidates_and_keeps_results():
     from paper_2102_06611_amd import autotune
     betas = linear_schedule(0.44, 10)
