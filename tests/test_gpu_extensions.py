@@ -576,6 +576,30 @@ def test_error_bars_fall_as_one_over_sqrt_population():
         assert np.all(np.abs(scaled[R] / ref - 1.0) < 0.25), scaled
 
 
+@pytest.mark.slow
+def test_effective_population_size_falls_linearly_with_the_step():
+    """Sec. "Statistical errors", Eq. Reff-deltabeta: close to criticality
+    (L = 64, beta = 0.43, R = 10000, averaged over independent runs) the
+    paper fits 1 - R_eff / R = A dbeta.  64 runs with theta = 40 per step
+    size dbeta = 0.0025, 0.005 and 0.01 (the last three steps of each run): the
+    slope (1 - R_eff / R) / dbeta is required to agree within 30 % across the
+    three step sizes."""
+    slopes = []
+    for db in (0.0025, 0.005, 0.01):
+        n = int(round(0.43 / db))
+        betas = np.linspace(0.0, 0.43, n + 1)
+        specs = [dict(L=64, R=10000, theta=40, seed=700 + s, betas=betas, resample="nearest")
+                 for s in range(64)]
+        b = pa.Batch(specs)
+        b.run(n)
+        y = np.mean([1.0 - b.observables(k, i)["r_eff_E"] / b.observables(k, i)["R_i"]
+                     for k in range(64) for i in range(n - 2, n + 1)])
+        b.close()
+        slopes.append(y / db)
+    log("(1 - R_eff/R) / dbeta", slopes)
+    assert max(slopes) < 1.3 * min(slopes), slopes
+
+
 def test_autotuner_times_candidates_and_keeps_results():
     from paper_2102_06611_amd import autotune
     betas = linear_schedule(0.44, 10)
