@@ -2308,9 +2308,11 @@ __device__ void record_run(const RunDesc &rd) {
     const int64_t sum_cnt2 = st->sum_cnt2;
     const int nF = min(kBlocks, rd.R);
     double jkF_own = 0.0, jkw_own = 0.0;
+    __shared__ double jw[kBlocks];  // the blocks' weight sums, for the complements below
     if ((int)threadIdx.x < nF) {
         jkF_own = st->jk_F[threadIdx.x];
         jkw_own = rd.jkw[threadIdx.x];
+        jw[threadIdx.x] = jkw_own;
     }
     // thread k < n: the blocking sums of block k (used below), cleared for the next step
     const int nbk = min(kBlocks, Rn);
@@ -2375,8 +2377,23 @@ __device__ void record_run(const RunDesc &rd) {
         double D = jkF_own;
         if (step > 0) {
             const int64_t lo = (int64_t)k * Rp / nF, hi = (int64_t)(k + 1) * Rp / nF;
-            D += hi - lo == Rp ? __builtin_nan("")
-                               : log1p(-jkw_own / S) - log1p(-(double)(hi - lo) / (double)Rp);
+            // ln of the weight outside block k over the total: log1p(-W_k / S),
+            // except where the block holds most of the weight, where 1 - W_k / S
+            // would cancel and the other blocks' own sum is taken instead (a
+            // block holding all but e^-20 of it would otherwise lose 7 digits)
+            const double x = jkw_own / S;
+            double lw;
+            if (x <= 0.5) {
+                lw = log1p(-x);
+            } else {
+                double rest = 0.0, all = 0.0;
+                for (int j = 0; j < nF; ++j) {
+                    all += jw[j];
+                    if (j != k) rest += jw[j];
+                }
+                lw = log(rest / all);
+            }
+            D += hi - lo == Rp ? __builtin_nan("") : lw - log1p(-(double)(hi - lo) / (double)Rp);
             st->jk_F[k] = D;
         }
         dF[k] = D;

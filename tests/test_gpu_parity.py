@@ -160,6 +160,9 @@ CASES = [
     # parent blocks' bases and the dense stretch ends instead of the LDS index
     # of every stretch
     (4, 300000, 1, 2, 0.6, "multinomial", "msc64"),
+    # L = 128 multinomial: the normalisation runs in its own launch (the
+    # weights kernel folds it in only up to L = 64), with a partial second group
+    (128, 130, 1, 3, 0.5, "multinomial", "msc64"),
     # Poisson resampling: fluctuating R_i, several blocks, strong selection
     (8, 200, 3, 8, 0.44, "poisson", "msc64"),
     (6, 130, 2, 6, 0.6, "poisson", "int8"),
