@@ -163,6 +163,12 @@ CASES = [
     # L = 128 multinomial: the normalisation runs in its own launch (the
     # weights kernel folds it in only up to L = 64), with a partial second group
     (128, 130, 1, 3, 0.5, "multinomial", "msc64"),
+    # strong selection at other sizes and with the other copy rules: one or a
+    # few parents take nearly all the weight in the first steps
+    (128, 130, 1, 3, 0.5, "nearest", "int8"),
+    (128, 100, 1, 3, 0.5, "poisson", "msc64"),
+    (64, 70, 2, 3, 1.0, "multinomial", "msc64"),
+    (32, 200, 1, 2, 1.5, "nearest", "msc64"),
     # Poisson resampling: fluctuating R_i, several blocks, strong selection
     (8, 200, 3, 8, 0.44, "poisson", "msc64"),
     (6, 130, 2, 6, 0.6, "poisson", "int8"),
