@@ -322,6 +322,9 @@ HEATBATH_CASES = [
     (12, 100, 2, linear_schedule(3.0, 4), "none", "msc64"),  # large beta: small T'
     (10, 1, 2, linear_schedule(0.5, 5), "nearest", "msc64"),
     (16, 150, 2, [0.0, 0.0, 0.0, 0.2, 0.4], "nearest", "msc64"),  # beta = 0: fair coins
+    # L = 128 and strong selection (normalisation in its own launch)
+    (128, 130, 1, linear_schedule(0.5, 3), "multinomial", "msc64"),
+    (64, 100, 2, linear_schedule(0.8, 3), "nearest", "int8"),
 ]
 
 
