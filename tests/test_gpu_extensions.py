@@ -56,6 +56,33 @@ def test_batch_of_uneven_runs_matches_single_runs_and_oracle():
     b.close()
 
 
+def test_batch_mixing_every_copy_rule_and_size_matches_single_runs():
+    """One batch holding L = 128 and 64 multinomial runs beside nearest, Poisson
+    and heatbath ones: the batch normalises every run in k_norm (a multinomial
+    run alone at L <= 64 folds it into its weights' launch instead), and every
+    record must equal that of the same run made alone."""
+    n = 4
+    specs = [dict(L=128, R=130, theta=1, seed=31, resample="multinomial", layout="msc64"),
+             dict(L=64, R=700, theta=2, seed=32, resample="multinomial", layout="int8"),
+             dict(L=64, R=300, theta=1, seed=33, resample="poisson", layout="msc64"),
+             dict(L=32, R=1000, theta=2, seed=34, resample="nearest", layout="msc64",
+                  update="heatbath"),
+             dict(L=8, R=65, theta=3, seed=35, resample="none", layout="int8")]
+    for k, s in enumerate(specs):
+        s["betas"] = linear_schedule(0.4 + 0.2 * k, n)
+    b = pa.Batch(specs)
+    b.run(n)
+    b.sync()
+    for k, s in enumerate(specs):
+        single = pa.Run(s["L"], s["R"], s["betas"], s["theta"], s["seed"], s["resample"],
+                        s["layout"], update=s.get("update", "metropolis"))
+        single.run(n)
+        for i in range(n + 1):
+            assert same_record(b.observables(k, i), single.observables(i)), (k, i)
+        single.close()
+    b.close()
+
+
 def _close_weighted(got, want, ctx):
     from oracle import weighted as wt
     assert got["step"] == want["step"] and got["n_runs"] == want["n_runs"], ctx
