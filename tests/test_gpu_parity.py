@@ -249,13 +249,16 @@ def test_same_seed_is_bit_identical_and_seed_matters():
     assert blobs[0] != blobs[2]
 
 
-def test_checkpoint_resume_is_bit_identical():
+@pytest.mark.parametrize("L,R,resample,layout,update", [(12, 500, "nearest", "int8", "metropolis"),
+                                                       (128, 700, "multinomial", "msc64", "metropolis"),
+                                                       (64, 300, "poisson", "int8", "heatbath")])
+def test_checkpoint_resume_is_bit_identical(L, R, resample, layout, update):
     betas = linear_schedule(0.6, 10)
-    a = pa.Run(12, 500, betas, 2, 3, "nearest", "int8")
+    a = pa.Run(L, R, betas, 2, 3, resample, layout, update=update)
     a.run(4)
     blob = a.get_state()
     a.run(6)
-    b = pa.Run(12, 500, betas, 2, 3, "nearest", "int8")
+    b = pa.Run(L, R, betas, 2, 3, resample, layout, update=update)
     b.set_state(blob)
     b.run(6)
     assert a.get_state() == b.get_state()
